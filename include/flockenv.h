@@ -1,0 +1,246 @@
+/*
+ * flockenv.h -- C ABI of the MI355X flock-environment step library.
+ *
+ * The environment is the "flock" multi-agent environment of Langham-Lopez,
+ * Schmon and Cannon, "High Performance Simulation for Scalable Multi-Agent
+ * Reinforcement Learning" (arXiv:2207.03945):
+ *   - Sec. 2.1: discrete time; every interaction updates all agents
+ *     simultaneously.
+ *   - Sec. 2.2: environment and learner share device memory directly, with no
+ *     copy through the host.
+ *   - Sec. 4: each agent's view is v sectors of its field of view, each
+ *     holding the distance to the nearest other agent at that bearing.
+ *   - Sec. 4.1: actions rotate the heading (at most theta_max) and change the
+ *     speed (clamped to [s_min, s_max]); reward Eq. (1) sums a contribution
+ *     over all agents closer than the vision range d_v, with a penalty for a
+ *     collision (Fig. 4); each update first applies the actions, then updates
+ *     the view and reward over all pairs in spatial proximity.
+ *   - Sec. 4.3 and 5: one policy network shared by all agents, two hidden
+ *     layers of 64 units.
+ *
+ * Conventions for every call below:
+ *   - Every pointer named in a "device" argument is device memory of the
+ *     current HIP device (for example a PyTorch CUDA tensor's data_ptr()).
+ *     "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; the caller synchronises.
+ *   - The library never allocates device memory.  All device memory is a
+ *     caller-owned workspace whose size the *_workspace_bytes call reports;
+ *     the workspace must stay alive, untouched by the caller, until the
+ *     object bound to it is destroyed.
+ *   - Return value: ENV_OK (0) on success, a negative ENV_E* code on error.
+ *     On error nothing is enqueued and no state changes; env_last_error()
+ *     returns a message for the calling thread.
+ *   - An object is used from one host thread and one stream at a time.
+ *
+ * State layout (structure of arrays, FP32, agent order): x[n], y[n] in
+ * [0, box), heading th[n] in [0, 2pi), speed s[n] in [s_min, s_max].
+ * Actions act[n][2]: column 0 = turn (rad), column 1 = speed change.
+ * View obs[n][v] (agent-major): 1 - d_min/radius per sector, 0 when empty.
+ * Reward reward[n] = r_nb * n_neighbours + r_col * n_collisions.
+ */
+#ifndef FLOCKENV_H
+#define FLOCKENV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
+enum {
+    ENV_OK = 0,
+    ENV_EINVAL = -1,   /* bad argument or parameter                      */
+    ENV_ENOMEM = -2,   /* workspace (or arena / budget) too small         */
+    ENV_ESTATE = -3,   /* call out of order (e.g. step before reset)     */
+    ENV_EHIP = -4,     /* HIP runtime error (message names the call)     */
+    ENV_EAGAIN = -5,   /* serving: request queued, no slot or memory yet */
+    ENV_ENOTFOUND = -6 /* serving: unknown request id                    */
+};
+
+/* flags */
+#define ENV_FLAG_COUNTS 1 /* keep per-agent neighbour / collision counts */
+
+/*
+ * Environment parameters (Sec. 4.1).  Requirements, else ENV_EINVAL:
+ * 0 <= n_agents <= 2^26; box finite and > 0; 0 < radius < box/2 (so the
+ * nearest periodic image is unique within the vision range);
+ * 0 <= collide <= radius; 1 <= sectors <= 256; max_turn, max_dspeed >= 0;
+ * 0 <= s_min <= s_max; all finite; cell_reach in {0, 1, 2} (0 = default 1):
+ * cells are at least radius/cell_reach wide, so a (2 cell_reach + 1)^2 block
+ * of cells covers the vision disc.  Boxes narrower than three cells use a
+ * single cell and compare all pairs; the result does not depend on this.
+ */
+typedef struct env_params {
+    int32_t n_agents;
+    float box;         /* side L of the periodic square box              */
+    float radius;      /* vision range d_v (Eq. (1))                     */
+    float collide;     /* collision distance 2 d_r (Fig. 4)              */
+    int32_t sectors;   /* v (Sec. 4)                                     */
+    float r_nb;        /* reward per neighbour within radius             */
+    float r_col;       /* reward per collision (negative = penalty)      */
+    float max_turn;    /* theta_max (Sec. 4.1)                           */
+    float max_dspeed;  /* a_max (Sec. 4.1)                               */
+    float s_min;       /* speed clamp (Sec. 4.1)                         */
+    float s_max;
+    int32_t cell_reach;
+    int32_t flags;     /* ENV_FLAG_*                                     */
+} env_params_t;
+
+typedef struct flock_env env_t;
+typedef struct flock_batch env_batch_t;
+typedef struct flock_policy pol_t;
+typedef struct flock_server srv_t;
+
+/* Thread-local message describing the last error ("" if none). */
+const char *env_last_error(void);
+
+/* ------------------------------------------------------------------ env */
+
+/* Device bytes one environment needs (state, FP64 returns, counts and the
+ * cell-list scratch of its own step).  0 if the parameters are invalid. */
+size_t env_workspace_bytes(const env_params_t *p);
+
+/* Bind an environment to `workspace` (device, >= env_workspace_bytes(p)
+ * bytes, 256-byte aligned).  Makes no HIP call.  *out receives a handle the
+ * caller releases with env_destroy.  ENV_EINVAL (bad params, NULL or
+ * misaligned pointer), ENV_ENOMEM (bytes too small). */
+int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out);
+
+/* Release the handle (not the workspace).  NULL is ignored. */
+void env_destroy(env_t *env);
+
+/* Effective cell grid: cells per side (1 = all-pairs), reach, cell side. */
+int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell);
+
+/* Copy a state in (device x, y, th, s, each [n] FP32).  Values must already
+ * lie in their ranges (positions in [0, box), heading in [0, 2pi)); they are
+ * not checked.  Enqueued on `stream`. */
+int env_set_state(env_t *env, const float *x, const float *y, const float *th,
+                  const float *s, void *stream);
+
+/* Copy the current state out (device x, y, th, s, each [n] FP32). */
+int env_get_state(env_t *env, float *x, float *y, float *th, float *s, void *stream);
+
+/* Start an episode from the current state: zero the FP64 returns and compute
+ * the initial view obs (device [n][v] FP32) without moving.  Requires a
+ * prior env_set_state, else ENV_ESTATE. */
+int env_reset(env_t *env, float *obs, void *stream);
+
+/* One step (Sec. 4.1 order): apply act (device [n][2]) to every agent, move,
+ * then write the view obs (device [n][v]) and reward (device [n]) of the new
+ * positions, and add the reward to the FP64 returns.  ENV_ESTATE before
+ * env_reset. */
+int env_step(env_t *env, const float *act, float *obs, float *reward, void *stream);
+
+/* Last step's per-agent neighbour / collision counts (device int32 [n]);
+ * requires ENV_FLAG_COUNTS, else ENV_ESTATE. */
+int env_get_counts(env_t *env, int32_t *n_nb, int32_t *n_col, void *stream);
+
+/* Per-agent undiscounted returns since env_reset (device FP64 [n]). */
+int env_get_returns(env_t *env, double *ret, void *stream);
+
+/* ---------------------------------------------------------------- batch */
+
+/* Several environments (possibly of different sizes and boxes, equal
+ * `sectors`) stepped together by one sequence of launches.  Agents of env k
+ * occupy rows [off[k], off[k+1]) of the batch-wide act/obs/reward arrays,
+ * with off[k] = sum of n_agents of envs 0..k-1 (see env_batch_offsets).
+ * Results are bitwise identical to stepping each env with env_step. */
+size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs);
+
+/* `ws` is device memory of >= env_batch_workspace_bytes bytes; the batch
+ * borrows the envs, which must outlive it.  Every env must have had
+ * env_reset.  ENV_EINVAL (n_envs < 1, NULL env, mixed sectors or flags),
+ * ENV_ENOMEM. */
+int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes,
+                     env_batch_t **out);
+void env_batch_destroy(env_batch_t *b);
+
+/* off[n_envs + 1] (host) receives the row offsets described above. */
+int env_batch_offsets(const env_batch_t *b, int64_t *off);
+
+/* One step of every env in the batch.  act: device [G][2], obs: device
+ * [G][v], reward: device [G], G = off[n_envs]. */
+int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward,
+                     void *stream);
+
+/* k_steps consecutive batched steps replayed from a captured HIP graph.
+ * act: device [k_steps][G][2] (step-major), obs: device [G][v] (final view),
+ * reward: device [k_steps][G].  The graph is captured on the first call and
+ * re-captured when any argument changes. */
+int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs,
+                  float *reward, void *stream);
+
+/* --------------------------------------------------------------- policy */
+
+/* Shared policy network of Sec. 4.3/5: in -> hidden -> hidden -> 2, tanh on
+ * every layer, output scaled by (max_turn, max_dspeed).  in must equal the
+ * envs' sector count and lie in [1, 32]; hidden = 64. */
+size_t pol_workspace_bytes(int in_dim, int hidden);
+
+/* w_host: FP32 host array W1[in][hidden], b1[hidden], W2[hidden][hidden],
+ * b2[hidden], W3[hidden][2], b3[2] (row-major, fan_in x fan_out).  Weights
+ * are rounded once to BF16 (round to nearest even) into `ws`; biases stay
+ * FP32.  Enqueued on `stream` (the copy is complete when the stream is). */
+int pol_create(const float *w_host, int in_dim, int hidden, float max_turn,
+               float max_dspeed, void *ws, size_t bytes, void *stream, pol_t **out);
+void pol_destroy(pol_t *pol);
+
+/* act[n][2] = policy(obs[n][in]) (device), BF16 MFMA, FP32 accumulate. */
+int pol_forward(pol_t *pol, const float *obs, int64_t n, float *act, void *stream);
+
+/* Closed-loop batched step: act = policy(obs) for every agent, then one
+ * batched step with those actions.  obs (device [G][v]) is read as the
+ * current view and overwritten by the new one; act (device [G][2]) receives
+ * the actions taken; reward (device [G]). */
+int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
+                    void *stream);
+
+/* -------------------------------------------------------------- serving */
+
+/* Continuous-batching server.  `arena` (device, `arena_bytes`) is the HBM
+ * budget: each admitted request's env workspace, view/action/reward rows and
+ * the tick's batch scratch are carved from it.  At most max_slots requests
+ * run at once.  All requests share `pol` and must have sectors == pol's in.
+ */
+int srv_create(void *arena, size_t arena_bytes, int max_slots, pol_t *pol,
+               void *stream, srv_t **out);
+void srv_destroy(srv_t *srv);
+
+/* Queue an episode request: parameters, initial state (host FP32 x, y, th,
+ * s, each [n]) and episode length.  Never blocks; *id receives the request
+ * id.  Returns ENV_OK when admitted at once, ENV_EAGAIN when queued (no slot
+ * or no memory yet), ENV_ENOMEM when the request could never fit. */
+int srv_submit(srv_t *srv, const env_params_t *p, const float *x, const float *y,
+               const float *th, const float *s, int steps, int64_t *id);
+
+/* One serving tick: admit queued requests that now fit, run one closed-loop
+ * batched step over all running requests, retire those that finished.
+ * *n_running / *agents receive the number of requests and agents stepped.
+ * Synchronises the stream at the end of the tick. */
+int srv_tick(srv_t *srv, int32_t *n_running, int64_t *agents);
+
+/* *state: 0 queued, 1 running, 2 finished; *steps_done: steps so far. */
+int srv_poll(srv_t *srv, int64_t id, int32_t *state, int32_t *steps_done);
+
+/* Per-agent FP64 returns of a finished request (host [n]); frees its record. */
+int srv_result(srv_t *srv, int64_t id, double *returns_host, int64_t n);
+
+/* Arena bytes one request with these parameters occupies (0 if invalid). */
+size_t srv_request_bytes(const env_params_t *p);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOCKENV_H */

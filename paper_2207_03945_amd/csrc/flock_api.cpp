@@ -1,0 +1,480 @@
+// flock_api.cpp -- the C ABI declared in include/flockenv.h: parameter
+// validation, cell-grid geometry, workspace carving and the env / batch
+// objects.  Every device computation is a kernel in flock_kernels.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "flock_internal.h"
+
+using namespace flock;
+
+// ----------------------------------------------------------------- errors
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(ENV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite(float v) { return isfinite(v) != 0; }
+
+// Largest agent count per env and per batch (row indices are int32).
+constexpr int64_t kMaxAgents = int64_t(1) << 26;
+constexpr int64_t kMaxBatchAgents = int64_t(1) << 30;
+// The two-level scan covers (16384 cells per tile) x (16384 tiles).
+constexpr int64_t kMaxBatchCells = int64_t(1) << 28;
+
+int check_params(const env_params_t *p) {
+    if (!p) return fail(ENV_EINVAL, "params is NULL");
+    if (p->n_agents < 0 || p->n_agents > kMaxAgents)
+        return fail(ENV_EINVAL, "n_agents %d outside [0, 2^26]", p->n_agents);
+    if (!finite(p->box) || !(p->box > 0.0f)) return fail(ENV_EINVAL, "box must be finite and > 0");
+    if (!finite(p->radius) || !(p->radius > 0.0f))
+        return fail(ENV_EINVAL, "radius must be finite and > 0");
+    if (!(p->radius < 0.5f * p->box))
+        return fail(ENV_EINVAL, "radius %g must be < box/2 (%g)", p->radius, 0.5f * p->box);
+    if (!finite(p->collide) || p->collide < 0.0f || p->collide > p->radius)
+        return fail(ENV_EINVAL, "collide must be in [0, radius]");
+    if (p->sectors < 1 || p->sectors > 256) return fail(ENV_EINVAL, "sectors must be in [1, 256]");
+    if (!finite(p->r_nb) || !finite(p->r_col)) return fail(ENV_EINVAL, "rewards must be finite");
+    if (!finite(p->max_turn) || p->max_turn < 0.0f || !finite(p->max_dspeed) || p->max_dspeed < 0.0f)
+        return fail(ENV_EINVAL, "max_turn and max_dspeed must be finite and >= 0");
+    if (!finite(p->s_min) || !finite(p->s_max) || p->s_min < 0.0f || p->s_min > p->s_max)
+        return fail(ENV_EINVAL, "need 0 <= s_min <= s_max");
+    if (p->cell_reach < 0 || p->cell_reach > 2) return fail(ENV_EINVAL, "cell_reach must be 0, 1 or 2");
+    if (p->flags & ~ENV_FLAG_COUNTS) return fail(ENV_EINVAL, "unknown flags 0x%x", p->flags);
+    return ENV_OK;
+}
+
+struct Geometry {
+    int ncell, reach;
+    float cell, inv_cell;
+};
+
+// Cells are at least radius/reach wide after FP32 rounding of the cell
+// boundaries: floor(x * inv_cell) moves a boundary by at most box * 2^-23,
+// so the nominal width carries a margin of 4 * box * 2^-23.  The grid is
+// also capped near sqrt(4n) cells per side so empty boxes stay cheap
+// (wider cells only add candidates).  Fewer than 2 reach + 1 cells per
+// side would visit a cell twice, so such boxes fall back to one cell and
+// all pairs.
+Geometry geometry(const env_params_t &p) {
+    Geometry g{1, 0, p.box, 0.0f};
+    const double L = p.box, R = p.radius;
+    const double margin = 4.0 * L * ldexp(1.0, -23);
+    const int64_t cap = (int64_t)ceil(sqrt(4.0 * (double)(p.n_agents > 0 ? p.n_agents : 1))) + 3;
+    for (int r = (p.cell_reach == 0 ? 1 : p.cell_reach); r >= 1; --r) {
+        int64_t nc = (int64_t)floor(L / (R / r + margin));
+        if (nc > cap) nc = cap;
+        if (nc > 8192) nc = 8192;
+        if (nc >= 2 * r + 1) {
+            g.ncell = (int)nc;
+            g.reach = r;
+            g.cell = (float)(L / (double)nc);
+            g.inv_cell = (float)((double)nc / L);
+            return g;
+        }
+    }
+    return g;
+}
+
+DevEnv make_desc(const env_params_t &p, const Geometry &gm) {
+    DevEnv d;
+    memset(&d, 0, sizeof(d));
+    d.n = p.n_agents;
+    d.ncell = gm.ncell;
+    d.reach = gm.reach;
+    d.box = p.box;
+    d.inv_cell = gm.inv_cell;
+    d.r2 = p.radius * p.radius;
+    d.c2 = p.collide * p.collide;
+    d.radius = p.radius;
+    d.r_nb = p.r_nb;
+    d.r_col = p.r_col;
+    d.max_turn = p.max_turn;
+    d.max_dspeed = p.max_dspeed;
+    d.s_min = p.s_min;
+    d.s_max = p.s_max;
+    d.sec_scale = (float)((double)p.sectors / 6.283185307179586476925286766559);
+    return d;
+}
+
+struct EnvLayout {
+    float *x, *y, *th, *s;
+    double *ret;
+    int32_t *nb, *col;
+    SortArrays sort;
+    size_t bytes;
+};
+
+EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
+    EnvLayout l;
+    Carver cv{base, 0};
+    const int64_t n = p.n_agents;
+    l.x = cv.take<float>(n);
+    l.y = cv.take<float>(n);
+    l.th = cv.take<float>(n);
+    l.s = cv.take<float>(n);
+    l.ret = cv.take<double>(n);
+    const bool counts = (p.flags & ENV_FLAG_COUNTS) != 0;
+    l.nb = counts ? cv.take<int32_t>(n) : nullptr;
+    l.col = counts ? cv.take<int32_t>(n) : nullptr;
+    carve_sort(cv, n, (int64_t)gm.ncell * gm.ncell, 1, &l.sort);
+    l.bytes = align_up(cv.off, 256);
+    return l;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+
+struct flock_env {
+    env_params_t p;
+    Geometry gm;
+    EnvLayout lay;
+    StepPlan plan;
+    DevEnv desc;          // host copy of this env's own descriptor
+    int32_t base_host[2]; // {0, n}
+    bool has_state = false;
+    bool reset_done = false;
+};
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int k = 0;
+    const float *act = nullptr;
+    float *obs = nullptr, *reward = nullptr;
+    hipStream_t stream = nullptr;
+};
+
+struct flock_batch {
+    std::vector<env_t *> envs;
+    std::vector<DevEnv> descs;
+    std::vector<int32_t> base;
+    std::vector<int64_t> off;
+    StepPlan plan;
+    bool uploaded = false;
+    GraphCache gc;
+};
+
+extern "C" {
+
+const char *env_last_error(void) { return g_err.c_str(); }
+
+size_t env_workspace_bytes(const env_params_t *p) {
+    if (check_params(p) != ENV_OK) return 0;
+    const Geometry gm = geometry(*p);
+    return carve_env(nullptr, *p, gm).bytes;
+}
+
+int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out) {
+    int rc = check_params(p);
+    if (rc != ENV_OK) return rc;
+    if (!out) return fail(ENV_EINVAL, "out is NULL");
+    if (!workspace) return fail(ENV_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(ENV_EINVAL, "workspace must be 256-byte aligned");
+    const Geometry gm = geometry(*p);
+    const size_t need = carve_env(nullptr, *p, gm).bytes;
+    if (bytes < need) return fail(ENV_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, need);
+    env_t *e = new env_t;
+    e->p = *p;
+    e->gm = gm;
+    e->lay = carve_env(static_cast<char *>(workspace), *p, gm);
+    e->desc = make_desc(*p, gm);
+    e->desc.x = e->lay.x;
+    e->desc.y = e->lay.y;
+    e->desc.th = e->lay.th;
+    e->desc.s = e->lay.s;
+    e->desc.ret = e->lay.ret;
+    e->desc.nb = e->lay.nb;
+    e->desc.col = e->lay.col;
+    e->desc.agent_base = 0;
+    e->desc.cell_base = 0;
+    e->base_host[0] = 0;
+    e->base_host[1] = p->n_agents;
+    e->plan.a = e->lay.sort;
+    e->plan.n_envs = 1;
+    e->plan.G = p->n_agents;
+    e->plan.C = (int64_t)gm.ncell * gm.ncell;
+    e->plan.v = p->sectors;
+    e->plan.flags = p->flags;
+    e->plan.scan_blocks = scan_blocks_for(e->plan.C);
+    *out = e;
+    g_err.clear();
+    return ENV_OK;
+}
+
+void env_destroy(env_t *env) { delete env; }
+
+int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (ncell) *ncell = env->gm.ncell;
+    if (reach) *reach = env->gm.reach;
+    if (cell) *cell = env->gm.cell;
+    return ENV_OK;
+}
+
+int env_set_state(env_t *env, const float *x, const float *y, const float *th, const float *s,
+                  void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    const int n = env->p.n_agents;
+    if (n > 0 && (!x || !y || !th || !s)) return fail(ENV_EINVAL, "state pointer is NULL");
+    hipError_t e = launch_copy_state(x, y, th, s, env->lay.x, env->lay.y, env->lay.th,
+                                     env->lay.s, n, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_set_state");
+    env->has_state = true;
+    return ENV_OK;
+}
+
+int env_get_state(env_t *env, float *x, float *y, float *th, float *s, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    const int n = env->p.n_agents;
+    if (n > 0 && (!x || !y || !th || !s)) return fail(ENV_EINVAL, "state pointer is NULL");
+    if (!env->has_state) return fail(ENV_ESTATE, "env has no state yet");
+    hipError_t e = launch_copy_state(env->lay.x, env->lay.y, env->lay.th, env->lay.s, x, y, th, s,
+                                     n, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_get_state");
+    return ENV_OK;
+}
+
+int env_reset(env_t *env, float *obs, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (!env->has_state) return fail(ENV_ESTATE, "env_reset before env_set_state");
+    const int n = env->p.n_agents;
+    if (n > 0 && !obs) return fail(ENV_EINVAL, "obs is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(env->lay.sort.envs, &env->desc, sizeof(DevEnv),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "env_reset: descriptor upload");
+    e = hipMemcpyAsync(env->lay.sort.base, env->base_host, sizeof(env->base_host),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "env_reset: base upload");
+    e = launch_clear(env->plan, s);
+    if (e != hipSuccess) return hip_fail(e, "env_reset: clear");
+    e = launch_zero_f64(env->lay.ret, n, s);
+    if (e != hipSuccess) return hip_fail(e, "env_reset: zero returns");
+    // The sense-only pass yields no reward: the episode's first reward comes
+    // with the first step.
+    e = launch_step(env->plan, 0, nullptr, obs, nullptr, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "env_reset: sense");
+    env->reset_done = true;
+    return ENV_OK;
+}
+
+int env_step(env_t *env, const float *act, float *obs, float *reward, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (!env->reset_done) return fail(ENV_ESTATE, "env_step before env_reset");
+    const int n = env->p.n_agents;
+    if (n > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    hipError_t e = launch_step(env->plan, 1, act, obs, reward, 1, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_step");
+    return ENV_OK;
+}
+
+int env_get_counts(env_t *env, int32_t *n_nb, int32_t *n_col, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (!(env->p.flags & ENV_FLAG_COUNTS)) return fail(ENV_ESTATE, "env created without ENV_FLAG_COUNTS");
+    if (!env->reset_done) return fail(ENV_ESTATE, "no step has run yet");
+    const int n = env->p.n_agents;
+    if (n > 0 && (!n_nb || !n_col)) return fail(ENV_EINVAL, "count pointer is NULL");
+    hipError_t e = launch_copy_i32(env->lay.nb, n_nb, n, as_stream(stream));
+    if (e == hipSuccess) e = launch_copy_i32(env->lay.col, n_col, n, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_get_counts");
+    return ENV_OK;
+}
+
+int env_get_returns(env_t *env, double *ret, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (!env->reset_done) return fail(ENV_ESTATE, "env_get_returns before env_reset");
+    const int n = env->p.n_agents;
+    if (n > 0 && !ret) return fail(ENV_EINVAL, "ret is NULL");
+    hipError_t e = launch_copy_f64(env->lay.ret, ret, n, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_get_returns");
+    return ENV_OK;
+}
+
+// ------------------------------------------------------------------- batch
+
+static int batch_layout(env_t *const *envs, int n_envs, std::vector<DevEnv> *descs,
+                        std::vector<int32_t> *base, std::vector<int64_t> *off, int64_t *G,
+                        int64_t *C, int *v) {
+    if (!envs || n_envs < 1) return fail(ENV_EINVAL, "need at least one env");
+    int64_t g = 0, c = 0;
+    for (int k = 0; k < n_envs; ++k) {
+        const env_t *e = envs[k];
+        if (!e) return fail(ENV_EINVAL, "env %d is NULL", k);
+        if (e->p.sectors != envs[0]->p.sectors)
+            return fail(ENV_EINVAL, "env %d has %d sectors, env 0 has %d", k, e->p.sectors,
+                        envs[0]->p.sectors);
+        if (descs) {
+            DevEnv d = e->desc;
+            d.agent_base = (int32_t)g;
+            d.cell_base = (int32_t)c;
+            descs->push_back(d);
+        }
+        if (base) base->push_back((int32_t)g);
+        if (off) off->push_back(g);
+        g += e->p.n_agents;
+        c += (int64_t)e->gm.ncell * e->gm.ncell;
+        if (g > kMaxBatchAgents || c > kMaxBatchCells)
+            return fail(ENV_EINVAL, "batch exceeds 2^30 agents or 2^28 cells");
+    }
+    if (base) base->push_back((int32_t)g);
+    if (off) off->push_back(g);
+    *G = g;
+    *C = c;
+    *v = envs[0]->p.sectors;
+    return ENV_OK;
+}
+
+size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs) {
+    int64_t G, C;
+    int v;
+    if (batch_layout(envs, n_envs, nullptr, nullptr, nullptr, &G, &C, &v) != ENV_OK) return 0;
+    Carver cv{nullptr, 0};
+    SortArrays a;
+    carve_sort(cv, G, C, n_envs, &a);
+    return align_up(cv.off, 256);
+}
+
+int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env_batch_t **out) {
+    if (!out) return fail(ENV_EINVAL, "out is NULL");
+    if (!ws) return fail(ENV_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(ENV_EINVAL, "workspace must be 256-byte aligned");
+    env_batch_t *b = new env_batch_t;
+    int64_t G, C;
+    int v;
+    int rc = batch_layout(envs, n_envs, &b->descs, &b->base, &b->off, &G, &C, &v);
+    if (rc != ENV_OK) {
+        delete b;
+        return rc;
+    }
+    for (int k = 0; k < n_envs; ++k) {
+        if (!envs[k]->reset_done) {
+            delete b;
+            return fail(ENV_ESTATE, "env %d has not been reset", k);
+        }
+    }
+    Carver cv{static_cast<char *>(ws), 0};
+    carve_sort(cv, G, C, n_envs, &b->plan.a);
+    if (bytes < align_up(cv.off, 256)) {
+        delete b;
+        return fail(ENV_ENOMEM, "batch workspace has %zu bytes, needs %zu", bytes,
+                    align_up(cv.off, 256));
+    }
+    b->envs.assign(envs, envs + n_envs);
+    b->plan.n_envs = n_envs;
+    b->plan.G = G;
+    b->plan.C = C;
+    b->plan.v = v;
+    b->plan.flags = 0;
+    b->plan.scan_blocks = scan_blocks_for(C);
+    *out = b;
+    return ENV_OK;
+}
+
+void env_batch_destroy(env_batch_t *b) {
+    if (!b) return;
+    if (b->gc.exec) (void)hipGraphExecDestroy(b->gc.exec);
+    if (b->gc.graph) (void)hipGraphDestroy(b->gc.graph);
+    delete b;
+}
+
+int env_batch_offsets(const env_batch_t *b, int64_t *off) {
+    if (!b || !off) return fail(ENV_EINVAL, "NULL argument");
+    for (size_t k = 0; k < b->off.size(); ++k) off[k] = b->off[k];
+    return ENV_OK;
+}
+
+static int batch_prepare(env_batch_t *b, hipStream_t s) {
+    if (b->uploaded) return ENV_OK;
+    hipError_t e = hipMemcpyAsync(b->plan.a.envs, b->descs.data(), b->descs.size() * sizeof(DevEnv),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->plan.a.base, b->base.data(), b->base.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_clear(b->plan, s);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    b->uploaded = true;
+    return ENV_OK;
+}
+
+int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward, void *stream) {
+    if (!b) return fail(ENV_EINVAL, "batch is NULL");
+    if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    hipStream_t s = as_stream(stream);
+    int rc = batch_prepare(b, s);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = launch_step(b->plan, 1, act, obs, reward, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "env_step_batched");
+    return ENV_OK;
+}
+
+int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
+                  void *stream) {
+    if (!b) return fail(ENV_EINVAL, "batch is NULL");
+    if (k_steps < 1) return fail(ENV_EINVAL, "k_steps must be >= 1");
+    if (!stream) return fail(ENV_EINVAL, "env_batch_run needs a non-null stream (graph capture)");
+    if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    hipStream_t s = as_stream(stream);
+    int rc = batch_prepare(b, s);
+    if (rc != ENV_OK) return rc;
+    GraphCache &gc = b->gc;
+    if (!gc.exec || gc.k != k_steps || gc.act != act || gc.obs != obs || gc.reward != reward ||
+        gc.stream != s) {
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+        if (gc.graph) (void)hipGraphDestroy(gc.graph);
+        gc = GraphCache{};
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const int64_t G = b->plan.G;
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < k_steps && le == hipSuccess; ++k)
+            le = launch_step(b->plan, 1, act + (size_t)k * G * 2, obs, reward + (size_t)k * G, 1, s);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le != hipSuccess ? le : e, "graph capture");
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        gc.exec = exec;
+        gc.graph = graph;
+        gc.k = k_steps;
+        gc.act = act;
+        gc.obs = obs;
+        gc.reward = reward;
+        gc.stream = s;
+    }
+    hipError_t e = hipGraphLaunch(gc.exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return ENV_OK;
+}
+
+}  // extern "C"

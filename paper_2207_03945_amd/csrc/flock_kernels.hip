@@ -1,0 +1,557 @@
+// flock_kernels.hip -- gfx950 kernels of one flock-environment step.
+//
+// One step (Sec. 4.1 of arXiv:2207.03945: apply the actions, then update
+// view and reward over every pair in spatial proximity; Sec. 2.1: all agents
+// update simultaneously) is four dependent phases over a whole batch of
+// environments at once:
+//
+//   k_move_count  rotate/accelerate/move/wrap each agent (FP32), compute its
+//                 cell, and take a rank in that cell with one atomic add
+//   k_scan_*      exclusive prefix of the per-cell counts (and re-zero them)
+//   k_scatter     counting-sort scatter: cell-ordered positions + headings
+//   k_sweep       one thread per agent in cell order walks the (2r+1)^2 cell
+//                 block round its own cell; per pair: periodic image, d^2,
+//                 radius tests, sector of the bearing, per-sector minimum in
+//                 LDS; then view, reward and the FP64 return
+//
+// Envs of a batch live in one global cell space (env k's cells start at
+// cell_base), so one counting sort serves every env and the cell-order range
+// of env k equals its row range [agent_base, agent_base + n).
+//
+// Arithmetic contract (compiled with -ffp-contract=off):
+//   * the move is IEEE FP32 operation by operation; cos/sin of the FP32
+//     heading are evaluated in double precision and rounded once, so the new
+//     state is the correctly rounded FP32 result of the stated operations;
+//   * pair displacement: the periodic shift is applied to whichever operand
+//     lies in the far half of the box, where the shift is exact, so dx and
+//     dy carry a single rounding; d^2 = dx*dx + dy*dy (no FMA); the radius
+//     tests are strict;
+//   * the bearing comes from rotating (dx, dy) into the heading frame and a
+//     FP32 atan2, so it is within about 2e-6 rad of the exact bearing.
+#include "flock_internal.h"
+
+namespace flock {
+
+namespace {
+
+constexpr uint32_t kInfBits = 0x7f800000u;
+
+// Positions lie in [0, L), so truncation is floor; the clamp keeps any
+// out-of-range or NaN coordinate inside the grid (memory safety only).
+__device__ __forceinline__ int cell_of(float v, float inv, int ncell) {
+    int c = (int)(v * inv);
+    c = c < ncell ? c : ncell - 1;
+    return c > 0 ? c : 0;
+}
+
+// Last env e with base[e] <= row (skips empty envs, whose base equals the next).
+__device__ __forceinline__ int env_search(const int32_t *base, int n_envs, int row) {
+    int lo = 0, hi = n_envs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// --------------------------------------------------------------------- move
+
+__global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, int n_envs, int G,
+                                                       int do_move, const float2 *__restrict__ act) {
+    __shared__ int s_env;
+    const int g0 = blockIdx.x * kBlock;
+    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, g0);
+    __syncthreads();
+    const int g = g0 + threadIdx.x;
+    if (g >= G) return;
+    int e = s_env;
+    while (a.base[e + 1] <= g) ++e;
+    const DevEnv &E = a.envs[e];
+    const int i = g - E.agent_base;
+
+    float x = E.x[i], y = E.y[i], h = E.th[i], sp = E.s[i];
+    if (do_move) {
+        const float2 av = act[g];
+        const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
+        const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
+        h = h + turn;
+        if (h < 0.0f) h = h + kTwoPiF;
+        if (h >= kTwoPiF) h = h - kTwoPiF;
+        sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+    }
+    double sd, cd;
+    sincos((double)h, &sd, &cd);
+    const float c = (float)cd, sn = (float)sd;
+    if (do_move) {
+        const float L = E.box;
+        float nx = x + sp * c;
+        if (nx < 0.0f) nx = nx + L;
+        if (nx >= L) nx = nx - L;
+        float ny = y + sp * sn;
+        if (ny < 0.0f) ny = ny + L;
+        if (ny >= L) ny = ny - L;
+        E.x[i] = nx;
+        E.y[i] = ny;
+        E.th[i] = h;
+        E.s[i] = sp;
+        x = nx;
+        y = ny;
+    }
+    const int cx = cell_of(x, E.inv_cell, E.ncell);
+    const int cy = cell_of(y, E.inv_cell, E.ncell);
+    const int key = E.cell_base + cx * E.ncell + cy;
+    a.slot[g] = atomicAdd(&a.count[key], 1);
+    a.key[g] = key;
+    a.tmp[g] = make_float4(x, y, c, sn);
+}
+
+// --------------------------------------------------------------------- scan
+
+// Exclusive block scan of one int per thread; also returns the block total.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) s_wave[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        int w = lane < NT / 64 ? s_wave[lane] : 0;
+        int wi = w;
+#pragma unroll
+        for (int d = 1; d < NT / 64; d <<= 1) {
+            int t = __shfl_up(wi, d, 64);
+            if (lane >= d) wi += t;
+        }
+        if (lane < NT / 64) s_wave[lane] = wi - w;
+        if (lane == NT / 64 - 1) s_wave[NT / 64] = wi;
+    }
+    __syncthreads();
+    const int r = s_wave[wid] + incl - v;
+    *total = s_wave[NT / 64];
+    return r;
+}
+
+constexpr int kScanNT = 1024;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanNT * kScanItems;  // cells per scan block
+
+// C <= kScanTile: one block does the whole scan and re-zeroes the counts.
+__global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ count,
+                                                         int32_t *__restrict__ start, int C) {
+    __shared__ int s_wave[kScanNT / 64 + 1];
+    const int t = threadIdx.x;
+    int vals[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int idx = k * kScanNT + t;  // coalesced: item-major
+        vals[k] = idx < C ? count[idx] : 0;
+    }
+    // thread t owns cells t*kScanItems .. : transpose through LDS for order
+    __shared__ int s_tile[kScanTile];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s_tile[k * kScanNT + t] = vals[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        vals[k] = s_tile[t * kScanItems + k];
+        sum += vals[k];
+    }
+    int total;
+    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        s_tile[t * kScanItems + k] = run;
+        run += vals[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int idx = k * kScanNT + t;
+        if (idx < C) {
+            start[idx] = s_tile[idx];
+            count[idx] = 0;
+        }
+    }
+    if (t == 0) start[C] = total;
+}
+
+// Large C, phase 1: per-tile sums; the last tile to finish scans the sums.
+__global__ __launch_bounds__(kScanNT) void k_scan_reduce(const int32_t *__restrict__ count,
+                                                         int32_t *__restrict__ part,
+                                                         uint32_t *__restrict__ ticket,
+                                                         int32_t *__restrict__ start, int C) {
+    __shared__ int s_wave[kScanNT / 64 + 1];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanNT + t;
+        sum += idx < C ? count[idx] : 0;
+    }
+    int total;
+    (void)block_exclusive_scan<kScanNT>(sum, s_wave, &total);
+    if (t == 0) {
+        part[blockIdx.x] = total;
+        __threadfence();
+        const uint32_t prev = atomicAdd(ticket, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // Last block: exclusive scan of the per-tile sums, kScanItems per thread.
+    const int nb = gridDim.x;  // <= kScanTile (checked on the host)
+    int vals[kScanItems];
+    int psum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int idx = t * kScanItems + k;
+        vals[k] = idx < nb ? __atomic_load_n(&part[idx], __ATOMIC_RELAXED) : 0;
+        psum += vals[k];
+    }
+    __syncthreads();
+    int grand;
+    int run = block_exclusive_scan<kScanNT>(psum, s_wave, &grand);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int idx = t * kScanItems + k;
+        if (idx < nb) part[idx] = run;
+        run += vals[k];
+    }
+    if (t == 0) {
+        start[C] = grand;
+        *ticket = 0u;
+    }
+}
+
+// Large C, phase 2: scan each tile with its offset; re-zero the counts.
+__global__ __launch_bounds__(kScanNT) void k_scan_down(int32_t *__restrict__ count,
+                                                       const int32_t *__restrict__ part,
+                                                       int32_t *__restrict__ start, int C) {
+    __shared__ int s_wave[kScanNT / 64 + 1];
+    __shared__ int s_tile[kScanTile];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanNT + t;
+        s_tile[k * kScanNT + t] = idx < C ? count[idx] : 0;
+    }
+    __syncthreads();
+    int vals[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        vals[k] = s_tile[t * kScanItems + k];
+        sum += vals[k];
+    }
+    int total;
+    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        s_tile[t * kScanItems + k] = run;
+        run += vals[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t idx = base + k * kScanNT + t;
+        if (idx < C) {
+            start[idx] = s_tile[k * kScanNT + t];
+            count[idx] = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ scatter
+
+__global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, int G) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= G) return;
+    const int pos = a.start[a.key[g]] + a.slot[g];
+    const float4 t = a.tmp[g];
+    a.sxy[pos] = make_float2(t.x, t.y);
+    a.scs[pos] = make_float2(t.z, t.w);
+    a.perm[pos] = g;
+}
+
+// -------------------------------------------------------------------- sweep
+
+struct PairAcc {
+    int nb, col;
+};
+
+// Test candidates [q0, q1) of cell order against agent p.  (offx, xi) and
+// (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis.
+template <int NT>
+__device__ __forceinline__ void sweep_run(const float2 *__restrict__ sxy, int q0, int q1, int p,
+                                          float offx, float xi, float offy, float yi, float r2,
+                                          float c2, float cth, float sth, float sec_scale, int v,
+                                          uint32_t *smin, PairAcc &acc) {
+    for (int q = q0; q < q1; ++q) {
+        const float2 pj = sxy[q];
+        const float dx = (pj.x + offx) - xi;
+        const float dy = (pj.y + offy) - yi;
+        const float d2 = dx * dx + dy * dy;
+        if (d2 < r2 && q != p) {
+            acc.nb += 1;
+            acc.col += d2 < c2 ? 1 : 0;
+            int k = 0;
+            if (d2 > 0.0f) {
+                const float u = dx * cth + dy * sth;
+                const float w = dy * cth - dx * sth;
+                float phi = atan2f(w, u);
+                if (phi < 0.0f) phi = phi + kTwoPiF;
+                k = (int)(phi * sec_scale);
+                k = k < v - 1 ? k : v - 1;
+            }
+            atomicMin(&smin[k * NT], __float_as_uint(d2));
+        }
+    }
+}
+
+// All-pairs run for single-cell envs: per candidate, shift the operand in the
+// far half of the box when the raw difference exceeds half the box.
+__device__ __forceinline__ float min_image_delta(float xj, float xi, float L) {
+    const float d = xj - xi;
+    if (d > 0.5f * L) return (xj - L) - xi;
+    if (d < -0.5f * L) return xj - (xi - L);
+    return d;
+}
+
+// NT threads per block; the per-thread sector minima take v * NT * 4 bytes of LDS.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, int v,
+                                              float *__restrict__ obs,
+                                              float *__restrict__ reward, int add_ret) {
+    extern __shared__ uint32_t s_min[];  // [v][NT]
+    __shared__ int s_env;
+    const int p0 = blockIdx.x * NT;
+    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    __syncthreads();
+    const int p = p0 + threadIdx.x;
+    if (p >= G) return;
+    int e = s_env;
+    while (a.base[e + 1] <= p) ++e;
+    const DevEnv &E = a.envs[e];
+
+    uint32_t *smin = s_min + threadIdx.x;
+    for (int k = 0; k < v; ++k) smin[k * NT] = kInfBits;
+
+    const float2 me = a.sxy[p];
+    const float2 cs = a.scs[p];
+    const float L = E.box, r2 = E.r2, c2 = E.c2, sec = E.sec_scale;
+    const int ncell = E.ncell, cb = E.cell_base;
+    PairAcc acc{0, 0};
+
+    if (ncell == 1) {
+        const int q0 = a.start[cb], q1 = a.start[cb + 1];
+        for (int q = q0; q < q1; ++q) {
+            if (q == p) continue;
+            const float2 pj = a.sxy[q];
+            const float dx = min_image_delta(pj.x, me.x, L);
+            const float dy = min_image_delta(pj.y, me.y, L);
+            const float d2 = dx * dx + dy * dy;
+            if (d2 < r2) {
+                acc.nb += 1;
+                acc.col += d2 < c2 ? 1 : 0;
+                int k = 0;
+                if (d2 > 0.0f) {
+                    const float u = dx * cs.x + dy * cs.y;
+                    const float w = dy * cs.x - dx * cs.y;
+                    float phi = atan2f(w, u);
+                    if (phi < 0.0f) phi = phi + kTwoPiF;
+                    k = (int)(phi * sec);
+                    k = k < v - 1 ? k : v - 1;
+                }
+                atomicMin(&smin[k * NT], __float_as_uint(d2));
+            }
+        }
+    } else {
+        const int reach = E.reach;
+        const int cx = cell_of(me.x, E.inv_cell, ncell);
+        const int cy = cell_of(me.y, E.inv_cell, ncell);
+        const int lo = cy - reach, hi = cy + reach;
+        for (int ox = -reach; ox <= reach; ++ox) {
+            int ccx = cx + ox;
+            float offx = 0.0f, xi = me.x;
+            if (ccx < 0) {
+                ccx += ncell;
+                offx = -L;
+            } else if (ccx >= ncell) {
+                ccx -= ncell;
+                xi = me.x - L;
+            }
+            const int colb = cb + ccx * ncell;
+            if (lo < 0) {
+                sweep_run<NT>(a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell], p, offx, xi,
+                          -L, me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi + 1], p, offx, xi, 0.0f, me.y,
+                          r2, c2, cs.x, cs.y, sec, v, smin, acc);
+            } else if (hi >= ncell) {
+                sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + ncell], p, offx, xi, 0.0f,
+                          me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi - ncell + 1], p, offx, xi, 0.0f,
+                          me.y - L, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+            } else {
+                sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + hi + 1], p, offx, xi, 0.0f,
+                          me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+            }
+        }
+    }
+
+    const int g = a.perm[p];
+    const int i = g - E.agent_base;
+    const float R = E.radius;
+    float *orow = obs + (size_t)g * v;
+    if ((v & 3) == 0) {
+        for (int k = 0; k < v; k += 4) {
+            float o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t m = smin[(k + j) * NT];
+                o[j] = m == kInfBits ? 0.0f : 1.0f - sqrtf(__uint_as_float(m)) / R;
+            }
+            *reinterpret_cast<float4 *>(orow + k) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+    } else {
+        for (int k = 0; k < v; ++k) {
+            const uint32_t m = smin[k * NT];
+            orow[k] = m == kInfBits ? 0.0f : 1.0f - sqrtf(__uint_as_float(m)) / R;
+        }
+    }
+    const float r = E.r_nb * (float)acc.nb + E.r_col * (float)acc.col;
+    if (reward) reward[g] = r;
+    if (add_ret) E.ret[i] += (double)r;
+    if (E.nb) {
+        E.nb[i] = acc.nb;
+        E.col[i] = acc.col;
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_clear(int32_t *count, int64_t C, uint32_t *ticket) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C) count[i] = 0;
+    if (i == 0) *ticket = 0u;
+}
+
+__global__ void k_copy_state(const float *sx, const float *sy, const float *sth, const float *ss,
+                             float *dx, float *dy, float *dth, float *ds, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dx[i] = sx[i];
+    dy[i] = sy[i];
+    dth[i] = sth[i];
+    ds[i] = ss[i];
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_copy_i32(const int32_t *src, int32_t *dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_copy_f64(const double *src, double *dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+}  // namespace
+
+int scan_blocks_for(int64_t C) { return C <= kScanTile ? 0 : (int)((C + kScanTile - 1) / kScanTile); }
+
+void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
+    const int nb = scan_blocks_for(C);
+    a->key = cv.take<int32_t>(G);
+    a->slot = cv.take<int32_t>(G);
+    a->tmp = cv.take<float4>(G);
+    a->sxy = cv.take<float2>(G);
+    a->scs = cv.take<float2>(G);
+    a->perm = cv.take<int32_t>(G);
+    a->count = cv.take<int32_t>(C);
+    a->start = cv.take<int32_t>(C + 1);
+    a->part = cv.take<int32_t>(nb + 1);
+    a->ticket = cv.take<uint32_t>(1);
+    a->envs = cv.take<DevEnv>(E);
+    a->base = cv.take<int32_t>(E + 1);
+}
+
+hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
+    const int64_t n = p.C > 0 ? p.C : 1;
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C,
+                       p.a.ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *obs,
+                       float *reward, int add_return, hipStream_t s) {
+    if (p.G == 0) return hipSuccess;
+    const int G = (int)p.G, C = (int)p.C;
+    const unsigned nb = blocks_for(G, kBlock);
+    hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, p.n_envs, G, do_move,
+                       reinterpret_cast<const float2 *>(act));
+    if (p.scan_blocks == 0) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanNT), 0, s, p.a.count, p.a.start, C);
+    } else {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScanNT), 0, s, p.a.count,
+                           p.a.part, p.a.ticket, p.a.start, C);
+        hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScanNT), 0, s, p.a.count,
+                           p.a.part, p.a.start, C);
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, G);
+    if (p.v <= 32) {
+        const size_t lds = (size_t)p.v * 256 * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_sweep<256>, dim3(blocks_for(G, 256)), dim3(256), lds, s, p.a,
+                           p.n_envs, G, p.v, obs, reward, add_return);
+    } else {
+        const size_t lds = (size_t)p.v * 64 * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_sweep<64>, dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a, p.n_envs,
+                           G, p.v, obs, reward, add_return);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const float *sx, const float *sy, const float *sth, const float *ss,
+                             float *dx, float *dy, float *dth, float *ds, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_state, dim3(blocks_for(n, 256)), dim3(256), 0, s, sx, sy, sth, ss,
+                       dx, dy, dth, ds, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace flock

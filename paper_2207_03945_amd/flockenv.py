@@ -1,0 +1,317 @@
+"""ctypes binding of ``libflockenv.so`` (declared in include/flockenv.h).
+
+Argument marshalling only: every step of the environment runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory (workspaces and the
+act/obs/reward tensors) and streams.  There is no CPU fallback: if the built
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflockenv.so")
+
+ENV_OK, ENV_EINVAL, ENV_ENOMEM, ENV_ESTATE, ENV_EHIP, ENV_EAGAIN, ENV_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+ENV_FLAG_COUNTS = 1
+
+_CODES = {ENV_EINVAL: "ENV_EINVAL", ENV_ENOMEM: "ENV_ENOMEM", ENV_ESTATE: "ENV_ESTATE",
+          ENV_EHIP: "ENV_EHIP", ENV_EAGAIN: "ENV_EAGAIN", ENV_ENOTFOUND: "ENV_ENOTFOUND"}
+
+
+class FlockError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class EnvParams(ctypes.Structure):
+    _fields_ = [("n_agents", ctypes.c_int32), ("box", ctypes.c_float), ("radius", ctypes.c_float),
+                ("collide", ctypes.c_float), ("sectors", ctypes.c_int32), ("r_nb", ctypes.c_float),
+                ("r_col", ctypes.c_float), ("max_turn", ctypes.c_float),
+                ("max_dspeed", ctypes.c_float), ("s_min", ctypes.c_float), ("s_max", ctypes.c_float),
+                ("cell_reach", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """Flock parameters (Sec. 4.1); defaults are the paper-scale workload's constants."""
+    n_agents: int
+    box: float
+    radius: float = 8.0
+    collide: float = 0.5
+    sectors: int = 16
+    r_nb: float = 0.1
+    r_col: float = -1.0
+    max_turn: float = 0.2
+    max_dspeed: float = 0.1
+    s_min: float = 0.0
+    s_max: float = 2.0
+    cell_reach: int = 0
+    flags: int = 0
+
+    def c(self) -> EnvParams:
+        return EnvParams(*[getattr(self, f.name) for f in fields(self)])
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def lib():
+    """Load the HIP library; raise ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2207_03945_amd/build.py "
+                          "(or __graft_entry__.build()) first; there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    ep = ctypes.POINTER(EnvParams)
+    sig = {
+        "env_last_error": (ctypes.c_char_p, []),
+        "env_workspace_bytes": (ctypes.c_size_t, [ep]),
+        "env_create": (ctypes.c_int, [ep, _P, ctypes.c_size_t, _PP]),
+        "env_destroy": (None, [_P]),
+        "env_geometry": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float)]),
+        "env_set_state": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+        "env_get_state": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+        "env_reset": (ctypes.c_int, [_P, _P, _P]),
+        "env_step": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+        "env_get_counts": (ctypes.c_int, [_P, _P, _P, _P]),
+        "env_get_returns": (ctypes.c_int, [_P, _P, _P]),
+        "env_batch_workspace_bytes": (ctypes.c_size_t, [_PP, ctypes.c_int]),
+        "env_batch_create": (ctypes.c_int, [_PP, ctypes.c_int, _P, ctypes.c_size_t, _PP]),
+        "env_batch_destroy": (None, [_P]),
+        "env_batch_offsets": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "env_step_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+        "env_batch_run": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+        "pol_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+        "pol_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                      ctypes.c_float, _P, ctypes.c_size_t, _P, _PP]),
+        "pol_destroy": (None, [_P]),
+        "pol_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+        "env_step_policy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+        "srv_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int, _P, _P, _PP]),
+        "srv_destroy": (None, [_P]),
+        "srv_submit": (ctypes.c_int, [_P, ep, _P, _P, _P, _P, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int64)]),
+        "srv_tick": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int64)]),
+        "srv_poll": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]),
+        "srv_result": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64]),
+        "srv_request_bytes": (ctypes.c_size_t, [ep]),
+    }
+    for name, (res, args) in sig.items():
+        if not hasattr(L, name):
+            continue
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().env_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc != ENV_OK:
+        raise FlockError(rc, last_error())
+    return rc
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _dev_f32(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def workspace_bytes(params: Params) -> int:
+    return int(lib().env_workspace_bytes(ctypes.byref(params.c())))
+
+
+class Env:
+    """One flock environment bound to a torch-allocated device workspace."""
+
+    def __init__(self, params: Params, device="cuda"):
+        self.params = params
+        self.n = params.n_agents
+        self.v = params.sectors
+        cp = params.c()
+        nbytes = lib().env_workspace_bytes(ctypes.byref(cp))
+        if nbytes == 0:
+            raise FlockError(ENV_EINVAL, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(lib().env_create(ctypes.byref(cp), self.workspace.data_ptr(), nbytes, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.env_destroy(h)
+            self.handle = None
+
+    def geometry(self):
+        nc, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        check(lib().env_geometry(self.handle, ctypes.byref(nc), ctypes.byref(r), ctypes.byref(c)))
+        return nc.value, r.value, c.value
+
+    def set_state(self, x, y, th, s, stream=None):
+        for t, nm in ((x, "x"), (y, "y"), (th, "th"), (s, "s")):
+            _dev_f32(t, (self.n,), nm)
+        check(lib().env_set_state(self.handle, _ptr(x), _ptr(y), _ptr(th), _ptr(s), _stream(stream)))
+
+    def get_state(self, stream=None):
+        out = [torch.empty(self.n, dtype=torch.float32, device=self.workspace.device) for _ in range(4)]
+        check(lib().env_get_state(self.handle, *[_ptr(t) for t in out], _stream(stream)))
+        return tuple(out)
+
+    def reset(self, obs=None, stream=None):
+        if obs is None:
+            obs = torch.empty(self.n, self.v, dtype=torch.float32, device=self.workspace.device)
+        _dev_f32(obs, (self.n, self.v), "obs")
+        check(lib().env_reset(self.handle, _ptr(obs), _stream(stream)))
+        return obs
+
+    def step(self, act, obs=None, reward=None, stream=None):
+        dev = self.workspace.device
+        if obs is None:
+            obs = torch.empty(self.n, self.v, dtype=torch.float32, device=dev)
+        if reward is None:
+            reward = torch.empty(self.n, dtype=torch.float32, device=dev)
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        check(lib().env_step(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
+        return obs, reward
+
+    def counts(self, stream=None):
+        dev = self.workspace.device
+        nb = torch.empty(self.n, dtype=torch.int32, device=dev)
+        col = torch.empty(self.n, dtype=torch.int32, device=dev)
+        check(lib().env_get_counts(self.handle, _ptr(nb), _ptr(col), _stream(stream)))
+        return nb, col
+
+    def returns(self, stream=None):
+        ret = torch.empty(self.n, dtype=torch.float64, device=self.workspace.device)
+        check(lib().env_get_returns(self.handle, _ptr(ret), _stream(stream)))
+        return ret
+
+
+class Batch:
+    """Several envs stepped together; rows of env k are offsets[k]:offsets[k+1]."""
+
+    def __init__(self, envs):
+        self.envs = list(envs)
+        arr = (ctypes.c_void_p * len(self.envs))(*[e.handle.value for e in self.envs])
+        self._arr = arr
+        pp = ctypes.cast(arr, _PP)
+        nbytes = lib().env_batch_workspace_bytes(pp, len(self.envs))
+        if nbytes == 0:
+            raise FlockError(ENV_EINVAL, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.envs[0].workspace.device)
+        h = ctypes.c_void_p()
+        check(lib().env_batch_create(pp, len(self.envs), self.workspace.data_ptr(), nbytes,
+                                     ctypes.byref(h)))
+        self.handle = h
+        off = (ctypes.c_int64 * (len(self.envs) + 1))()
+        check(lib().env_batch_offsets(self.handle, off))
+        self.offsets = list(off)
+        self.n = self.offsets[-1]
+        self.v = self.envs[0].v
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.env_batch_destroy(h)
+            self.handle = None
+
+    def step(self, act, obs, reward, stream=None):
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        check(lib().env_step_batched(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
+
+    def run(self, k_steps, act, obs, reward, stream):
+        """k_steps steps replayed from a HIP graph; ``stream`` must not be the null stream."""
+        _dev_f32(act, (k_steps, self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (k_steps, self.n), "reward")
+        check(lib().env_batch_run(self.handle, k_steps, _ptr(act), _ptr(obs), _ptr(reward),
+                                  _stream(stream)))
+
+    def step_policy(self, policy, act, obs, reward, stream=None):
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        check(lib().env_step_policy(self.handle, policy.handle, _ptr(act), _ptr(obs), _ptr(reward),
+                                    _stream(stream)))
+
+
+def pack_policy_weights(weights, biases):
+    """Flatten W1, b1, W2, b2, W3, b3 (fan_in x fan_out, row-major) into one FP32 host array."""
+    import numpy as np
+    parts = []
+    for w, b in zip(weights, biases):
+        parts.append(np.ascontiguousarray(w, dtype=np.float32).ravel())
+        parts.append(np.ascontiguousarray(b, dtype=np.float32).ravel())
+    return np.ascontiguousarray(np.concatenate(parts), dtype=np.float32)
+
+
+class Policy:
+    """Shared policy network (in -> 64 -> 64 -> 2, tanh) in BF16 on MFMA."""
+
+    def __init__(self, weights, biases, max_turn=0.2, max_dspeed=0.1, device="cuda", stream=None):
+        in_dim, hidden = weights[0].shape
+        self.in_dim, self.hidden = int(in_dim), int(hidden)
+        self._host = pack_policy_weights(weights, biases)
+        nbytes = lib().pol_workspace_bytes(self.in_dim, self.hidden)
+        if nbytes == 0:
+            raise FlockError(ENV_EINVAL, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(lib().pol_create(self._host.ctypes.data, self.in_dim, self.hidden, max_turn,
+                               max_dspeed, self.workspace.data_ptr(), nbytes, _stream(stream),
+                               ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.pol_destroy(h)
+            self.handle = None
+
+    def forward(self, obs, act=None, stream=None):
+        n = obs.shape[0]
+        if act is None:
+            act = torch.empty(n, 2, dtype=torch.float32, device=obs.device)
+        _dev_f32(obs, (n, self.in_dim), "obs")
+        _dev_f32(act, (n, 2), "act")
+        check(lib().pol_forward(self.handle, _ptr(obs), n, _ptr(act), _stream(stream)))
+        return act

@@ -18,3 +18,12 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each GPU test on the real stderr before it runs (survives a lost box)."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"\n[gpu-test] start {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield

@@ -1,0 +1,334 @@
+"""GPU parity: the HIP step against the CPU oracle, through the C ABI.
+
+Every case draws seeded synthetic inputs from ``workloads``; the oracle sees
+the same FP32 state and actions as the GPU.  The post-move state must match
+bitwise; counts, view and reward must match within the bands of
+``tests/parity.py``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from parity import EPS_D, EPS_PHI, check_sense, state_mismatch
+
+pytestmark = pytest.mark.gpu
+
+flock = pytest.importorskip("paper_2207_03945_amd")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_env(state, box, v, reach=0, flags=1):
+    n = state[0].shape[0]
+    env = flock.Env(flock.Params(n_agents=n, box=box, sectors=v, flags=flags, cell_reach=reach))
+    env.set_state(*[dev(a) for a in state])
+    obs0 = env.reset()
+    return env, obs0
+
+
+def band(state, box, v, agents=None):
+    return oracle.oracle_sense(state[0], state[1], state[2], box, sectors=v, agents=agents,
+                               eps_d=EPS_D, eps_phi=EPS_PHI)
+
+
+def gpu_state(env):
+    return tuple(host(t) for t in env.get_state())
+
+
+def check_step(env, st_oracle, box, v, obs, rew, agents=None, label=""):
+    torch.cuda.synchronize()
+    st_gpu = gpu_state(env)
+    bad, ulp = state_mismatch(st_gpu, st_oracle)
+    assert bad.size == 0, f"{label}: state differs at {bad[:10]} (max {ulp} ulp)"
+    nb, col = (host(t) for t in env.counts())
+    o = band(st_oracle, box, v, agents)
+    rows = slice(None) if agents is None else agents
+    return check_sense(o, host(obs)[rows], host(rew)[rows], nb[rows], col[rows], label=label)
+
+
+# --------------------------------------------------------------------------- reset
+
+@pytest.mark.parametrize("name", ["flock256", "flock5k"])
+def test_reset_view(name):
+    cfg = workloads.WORKLOADS[name]
+    st = workloads.make_state(name, seed=0)
+    env, obs0 = make_env(st, cfg["box"], cfg["sectors"])
+    torch.cuda.synchronize()
+    nb, col = (host(t) for t in env.counts())
+    o = band(st, cfg["box"], cfg["sectors"])
+    zero_rew = np.zeros(cfg["n"])
+    check_sense(o, host(obs0), 0.1 * nb - col, nb, col, label=f"{name} reset")
+    assert (zero_rew == host(env.returns())).all()
+
+
+# --------------------------------------------------------------------------- full runs
+
+def test_flock256_all_steps():
+    """256 agents, 64 x 64, 8 sectors, 100 steps: every step, every agent."""
+    cfg = workloads.WORKLOADS["flock256"]
+    box, v, n = cfg["box"], cfg["sectors"], cfg["n"]
+    st = workloads.make_state("flock256", seed=0)
+    env, _ = make_env(st, box, v)
+    obs = torch.empty(n, v, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    ret_oracle = np.zeros(n)
+    for t in range(cfg["steps"]):
+        act = workloads.random_actions(n, seed=0, step=t)
+        env.step(dev(act), obs, rew)
+        st = oracle.oracle_move(st, act, box)
+        check_step(env, st, box, v, obs, rew, label=f"flock256 step {t}")
+        ret_oracle += band(st, box, v).reward
+    ret = host(env.returns())
+    np.testing.assert_allclose(ret, ret_oracle, rtol=1e-5, atol=1e-5)
+
+
+def _run_sampled(name, check_at, n_sample, seed=0):
+    cfg = workloads.WORKLOADS[name]
+    box, v, n = cfg["box"], cfg["sectors"], cfg["n"]
+    st = workloads.make_state(name, seed=seed)
+    env, _ = make_env(st, box, v)
+    obs = torch.empty(n, v, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    g = np.random.default_rng(seed + 99)
+    last = max(check_at)
+    stats = []
+    for t in range(last + 1):
+        act = workloads.random_actions(n, seed=seed, step=t)
+        env.step(dev(act), obs, rew)
+        st = oracle.oracle_move(st, act, box)
+        if t in check_at:
+            agents = np.sort(g.choice(n, size=min(n_sample, n), replace=False)).astype(np.int32)
+            stats.append(check_step(env, st, box, v, obs, rew, agents=agents, label=f"{name} step {t}"))
+    return stats
+
+
+def test_flock5k_sampled_steps():
+    """5,000 agents, side 316, 16 sectors, 1,000 steps; all agents at six steps."""
+    _run_sampled("flock5k", {0, 1, 2, 10, 100, 999}, 5000)
+
+
+def test_blobs50k_sampled_steps():
+    """50,000 agents in 64 blobs, side 1,000, 500 steps; 3,000 sampled agents at six steps."""
+    _run_sampled("blobs50k", {0, 1, 2, 10, 100, 499}, 3000)
+
+
+def test_uniform50k_sampled_steps():
+    _run_sampled("uniform50k", {0, 1, 5}, 3000)
+
+
+# --------------------------------------------------------------------------- edge cases
+
+def _one_step_case(st, box, v, reach=0, steps=3, seed=0):
+    n = st[0].shape[0]
+    env, obs0 = make_env(st, box, v, reach=reach)
+    torch.cuda.synchronize()
+    if n > 0:
+        nb, col = (host(t) for t in env.counts())
+        check_sense(band(st, box, v), host(obs0), 0.1 * nb - col, nb, col, label="reset")
+    obs = torch.empty(n, v, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    for t in range(steps):
+        act = workloads.random_actions(n, seed=seed, step=t)
+        env.step(dev(act), obs, rew)
+        st = oracle.oracle_move(st, act, box)
+        if n > 0:
+            check_step(env, st, box, v, obs, rew, label=f"step {t}")
+    torch.cuda.synchronize()
+    return env
+
+
+def test_empty_env():
+    st = tuple(np.zeros(0, np.float32) for _ in range(4))
+    _one_step_case(st, 64.0, 8)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_envs(n):
+    st = workloads.uniform_state(n, 20.0, seed=n)
+    _one_step_case(st, 20.0, 8)
+
+
+@pytest.mark.parametrize("box", [16.5, 20.0, 24.0, 24.5, 33.0])
+def test_small_boxes_all_pairs_and_three_cells(box):
+    n = int(box * box / 4)
+    st = workloads.uniform_state(n, box, seed=3)
+    env = _one_step_case(st, box, 16)
+    ncell, reach, _ = env.geometry()
+    assert (ncell == 1) == (box <= 24.0)
+    assert ncell == 1 or ncell >= 3
+
+
+@pytest.mark.parametrize("v", [1, 3, 8, 16, 33, 64, 128, 256])
+def test_sector_counts(v):
+    st = workloads.uniform_state(2000, 120.0, seed=v)
+    _one_step_case(st, 120.0, v, steps=2)
+
+
+def test_reach_two_stencil():
+    st = workloads.uniform_state(4000, 160.0, seed=4)
+    env = _one_step_case(st, 160.0, 16, reach=2)
+    assert env.geometry()[1] == 2
+
+
+def test_dense_cluster_and_coincident():
+    """Skewed occupancy: most agents inside one cell, many exact duplicates."""
+    g = np.random.default_rng(5)
+    n, box = 3000, 200.0
+    x = (100.0 + g.random(n) * 3.0).astype(np.float32)
+    y = (50.0 + g.random(n) * 3.0).astype(np.float32)
+    x[::7] = x[0]
+    y[::7] = y[0]
+    th = (g.random(n) * 6.28).astype(np.float32)
+    s = np.zeros(n, np.float32)
+    _one_step_case((x, y, th, s), box, 16, steps=2)
+
+
+def test_cell_boundaries_and_seams():
+    """Agents exactly on cell boundaries, at 0 and just below the box side."""
+    box, v = 64.0, 16
+    env0 = flock.Env(flock.Params(n_agents=10000, box=box, sectors=v))
+    ncell, _, cell = env0.geometry()
+    xs = np.array([k * cell for k in range(ncell)] + [0.0, np.nextafter(np.float32(box), np.float32(0))],
+                  np.float32)
+    xx, yy = np.meshgrid(xs, xs, indexing="ij")
+    x, y = xx.ravel().astype(np.float32), yy.ravel().astype(np.float32)
+    n = x.shape[0]
+    th = (np.arange(n) * 0.37 % 6.2).astype(np.float32)
+    s = np.zeros(n, np.float32)
+    _one_step_case((x, y, th, s), box, v, steps=2)
+
+
+def test_single_large_env():
+    """2^20 agents in one env (side 4,096): sampled agents after two steps."""
+    n, box, v = 1 << 20, 4096.0, 16
+    st = workloads.uniform_state(n, box, seed=8)
+    env, _ = make_env(st, box, v)
+    obs = torch.empty(n, v, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    for t in range(2):
+        act = workloads.random_actions(n, seed=8, step=t)
+        env.step(dev(act), obs, rew)
+        st = oracle.oracle_move(st, act, box)
+    agents = np.sort(np.random.default_rng(1).choice(n, 2000, replace=False)).astype(np.int32)
+    check_step(env, st, box, v, obs, rew, agents=agents, label="1M env")
+
+
+# --------------------------------------------------------------------------- batched
+
+def _uneven(n_envs, lo, hi, seed):
+    ns, boxes = workloads.uneven_env_sizes(n_envs, lo, hi, seed=seed)
+    states = [workloads.uniform_state(int(n), float(b), seed=seed, env=k)
+              for k, (n, b) in enumerate(zip(ns, boxes))]
+    return ns, boxes, states
+
+
+def test_batched_equals_plain_bitwise():
+    ns, boxes, states = _uneven(12, 20, 3000, seed=21)
+    # add an empty env, a single-cell env and a reach-2 env
+    extra = [(0, 64.0, 0), (150, 20.0, 0), (800, 100.0, 2)]
+    envs_a, envs_b, boxes_all, states_all = [], [], [], []
+    for k, (n, b) in enumerate(zip(ns, boxes)):
+        boxes_all.append(float(b))
+        states_all.append(states[k])
+    for n, b, r in extra:
+        boxes_all.append(b)
+        states_all.append(workloads.uniform_state(n, b, seed=5))
+    reaches = [0] * len(ns) + [e[2] for e in extra]
+    for st, b, r in zip(states_all, boxes_all, reaches):
+        envs_a.append(make_env(st, b, 16, reach=r)[0])
+        envs_b.append(make_env(st, b, 16, reach=r)[0])
+    batch = flock.Batch(envs_b)
+    G = batch.n
+    obs_b = torch.empty(G, 16, device="cuda")
+    rew_b = torch.empty(G, device="cuda")
+    off = batch.offsets
+    for t in range(4):
+        acts = [workloads.random_actions(st[0].shape[0], seed=1, step=t, env=k)
+                for k, st in enumerate(states_all)]
+        act_b = dev(np.concatenate(acts).reshape(G, 2))
+        batch.step(act_b, obs_b, rew_b)
+        for k, env in enumerate(envs_a):
+            o, r = env.step(dev(acts[k]))
+            assert torch.equal(o, obs_b[off[k]:off[k + 1]]), f"obs env {k} step {t}"
+            assert torch.equal(r, rew_b[off[k]:off[k + 1]]), f"reward env {k} step {t}"
+    for ea, eb in zip(envs_a, envs_b):
+        assert torch.equal(ea.returns(), eb.returns())
+        for u, w in zip(ea.get_state(), eb.get_state()):
+            assert torch.equal(u, w)
+
+
+def test_batched_uneven_256_envs_against_oracle():
+    """256 envs, N_e log-uniform in [100, 20,000] at density 1/16: sampled agents per env."""
+    ns, boxes, states = _uneven(256, 100, 20000, seed=0)
+    envs = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
+    batch = flock.Batch(envs)
+    G = batch.n
+    off = batch.offsets
+    obs = torch.empty(G, 16, device="cuda")
+    rew = torch.empty(G, device="cuda")
+    acts = [workloads.random_actions(int(n), seed=0, step=0, env=k) for k, n in enumerate(ns)]
+    batch.step(dev(np.concatenate(acts)), obs, rew)
+    torch.cuda.synchronize()
+    obs_h, rew_h = host(obs), host(rew)
+    g = np.random.default_rng(3)
+    for k in range(256):
+        st = oracle.oracle_move(states[k], acts[k], float(boxes[k]))
+        bad, _ = state_mismatch(gpu_state(envs[k]), st)
+        assert bad.size == 0, f"env {k}"
+        agents = np.sort(g.choice(int(ns[k]), size=min(8, int(ns[k])), replace=False)).astype(np.int32)
+        nb, col = (host(t) for t in envs[k].counts())
+        o = band(st, float(boxes[k]), 16, agents)
+        rows = off[k] + agents
+        check_sense(o, obs_h[rows], rew_h[rows], nb[agents], col[agents], label=f"env {k}")
+
+
+def test_graph_replay_matches_eager():
+    ns, boxes, states = _uneven(10, 50, 2000, seed=7)
+    envs_g = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
+    envs_e = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
+    bg, be = flock.Batch(envs_g), flock.Batch(envs_e)
+    G, K = bg.n, 5
+    stream = torch.cuda.Stream()
+    obs_g = torch.empty(G, 16, device="cuda")
+    rew_g = torch.empty(K, G, device="cuda")
+    obs_e = torch.empty(G, 16, device="cuda")
+    rew_e = torch.empty(G, device="cuda")
+    for rep in range(3):
+        act = torch.stack([dev(np.concatenate([workloads.random_actions(int(n), seed=rep, step=t, env=k)
+                                               for k, n in enumerate(ns)])) for t in range(K)])
+        act = act.contiguous()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            bg.run(K, act, obs_g, rew_g, stream)
+        stream.synchronize()
+        for t in range(K):
+            be.step(act[t].contiguous(), obs_e, rew_e)
+            torch.cuda.synchronize()
+            assert torch.equal(rew_e, rew_g[t]), f"rep {rep} step {t}"
+        assert torch.equal(obs_e, obs_g)
+        # eager work between replays
+        _ = (obs_e * 2).sum().item()
+    for a, b in zip(envs_g, envs_e):
+        assert torch.equal(a.returns(), b.returns())
+
+
+def test_returns_accumulate_fp64():
+    st = workloads.uniform_state(500, 90.0, seed=2)
+    env, _ = make_env(st, 90.0, 16)
+    acc = np.zeros(500)
+    for t in range(20):
+        _, r = env.step(dev(workloads.random_actions(500, seed=2, step=t)))
+        acc += host(r).astype(np.float64)
+    np.testing.assert_array_equal(host(env.returns()), acc)

@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the flock-environment step on one MI355X: batched vs plain.
+
+Workload (the `value`): 200 independent 5,000-agent flock envs (periodic box
+of side 316, vision 8, collision 0.5, 16 sectors, seeded uniform actions
+turn in [-0.2, 0.2], dspeed in [-0.1, 0.1]) stepped together by one batched
+step; K steps replayed from one captured HIP graph, actions resident in HBM.
+A "step" is the whole step path: move + cell count, scan, scatter, sweep
+(view, reward, FP64 return) for every agent of every env.
+
+Also reported on the same JSON line:
+  plain      one 5,000-agent env stepped alone (p50/p99 per-step latency)
+  flock50k   the 50,000-agent clustered env (64 blobs) and a uniform 50,000-agent
+             env, plain and batched x20
+  roofline   the dominant kernel (the neighbour sweep), its algorithmic bytes
+             per launch over its average HIP-event duration on the stream
+  cpu_baseline  the CPU oracle on the host cores on a bounded sample
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+V = 16                     # sectors of the paper-scale workloads
+STEP_BYTES = 44 + 4 * V    # algorithmic bytes per agent-step of the whole step
+SWEEP_BYTES = 8 + 4 + 4 * V + 4 + 16   # per agent: position, heading, view, reward, FP64 return r/w
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def make_envs(flock, workloads, n, box, count, init, seed0):
+    envs = []
+    import torch
+    for k in range(count):
+        if init == "blobs":
+            st = workloads.blob_state(n, box, seed=seed0 + k)
+        else:
+            st = workloads.uniform_state(n, box, seed=seed0 + k)
+        env = flock.Env(flock.Params(n_agents=n, box=box, sectors=V))
+        env.set_state(*[torch.from_numpy(a).cuda() for a in st])
+        env.reset()
+        envs.append(env)
+    return envs
+
+
+def device_actions(G, K, seed):
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    a = torch.rand(K, G, 2, device="cuda", generator=g) * 2.0 - 1.0
+    a[..., 0] *= 0.2
+    a[..., 1] *= 0.1
+    return a.contiguous()
+
+
+def bench_batched(flock, batch, K, W, seed, timed_reps=20):
+    """Graph-replayed K-step run + per-phase timing; returns a dict."""
+    import torch
+    G = batch.n
+    act = device_actions(G, K, seed)
+    obs = torch.empty(G, V, device="cuda")
+    rew = torch.empty(K, G, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for t in range(W):
+            batch.step(act[t % K], obs, rew[t % K], stream)
+        # per-step latency of eager batched steps + per-phase durations
+        phases = []
+        lat = []
+        for t in range(timed_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ph = batch.step_timed(act[t % K], obs, rew[t % K], stream)
+            e1.record(stream)
+            stream.synchronize()
+            lat.append(e0.elapsed_time(e1))
+            phases.append(ph)
+        batch.capture(K, act, obs, rew, stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.run(K, act, obs, rew, stream)
+        stream.synchronize()
+        t1 = time.perf_counter()
+    assert torch.isfinite(obs).all() and torch.isfinite(rew).all()
+    el = t1 - t0
+    ph = np.mean(np.asarray(phases), axis=0)
+    return {"agent_steps_per_s": G * K / el, "ms_per_step": 1e3 * el / K, "agents": G,
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "phase_ms": {"move_count": float(ph[0]), "scan": float(ph[1]),
+                         "scatter": float(ph[2]), "sweep": float(ph[3])}}
+
+
+def bench_plain(env, n, K, W, seed):
+    import torch
+    act = device_actions(n, K, seed)
+    obs = torch.empty(n, V, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    for t in range(W):
+        env.step(act[t % K], obs, rew)
+    torch.cuda.synchronize()
+    # throughput: K back-to-back steps
+    t0 = time.perf_counter()
+    for t in range(K):
+        env.step(act[t], obs, rew)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # latency: each step bracketed by events
+    lat = []
+    for t in range(K):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        env.step(act[t], obs, rew)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    return {"agent_steps_per_s": n * K / el, "ms_per_step": 1e3 * el / K, "agents": n,
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
+
+
+def cpu_baseline(seconds):
+    """The oracle (all-pairs, FP64 view) on the host, 5,000-agent env, bounded sample."""
+    import oracle
+    import workloads
+    oracle.build()
+    n, box = 5000, 316.0
+    st = workloads.uniform_state(n, box, seed=0)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and steps < 1000:
+        act = workloads.random_actions(n, seed=0, step=steps)
+        st, _ = oracle.oracle_step(st, act, box, sectors=V)
+        steps += 1
+    el = time.perf_counter() - t0
+    return {"value": n * steps / el, "unit": "agent-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one 5,000-agent env (side 316, 16 sectors), first {steps} steps "
+                      f"(move + all-pairs view/reward), {el:.1f} s"}
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2207_03945_amd", "csrc", "flock_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(agents):
+    """HBM bytes per sweep launch from the committed PMC summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", "sweep_flock5k_x200_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != sweep_source_hash() or t.get("agents") != agents:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--envs", type=int, default=200, help="5,000-agent envs in the batch")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-main", action="store_true", help="skip the 50k and plain legs")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the flock step has no multi-GPU path in this "
+              "build (independent envs would shard across GPUs with no communication); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2207_03945_amd as flock
+    import workloads
+
+    flock.lib()
+    K, W = args.steps, args.warmup
+    torch.cuda.init()
+
+    log(f"[bench] batched 5k x {args.envs}")
+    envs = make_envs(flock, workloads, 5000, 316.0, args.envs, "uniform", 1000)
+    batch = flock.Batch(envs)
+    torch.cuda.synchronize()
+    # barrier + synchronize bracket the timed region inside bench_batched
+    main_res = bench_batched(flock, batch, K, W, seed=1)
+    G = batch.n
+    del batch
+    extra = {}
+    if not args.only_main:
+        log("[bench] plain 5k")
+        extra["plain"] = bench_plain(envs[0], 5000, K, W, seed=2)
+        del envs
+        for name, init in (("blobs50k", "blobs"), ("uniform50k", "uniform")):
+            log(f"[bench] {name} plain")
+            e50 = make_envs(flock, workloads, 50000, 1000.0, 20, init, 2000)
+            plain = bench_plain(e50[0], 50000, K, W, seed=3)
+            log(f"[bench] {name} batched x20")
+            b50 = flock.Batch(e50)
+            bat = bench_batched(flock, b50, K, W, seed=4, timed_reps=10)
+            extra[name] = {"plain": plain, "batched_x20": bat}
+            del b50, e50
+    else:
+        del envs
+
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 18, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    sweep_ms = main_res["phase_ms"]["sweep"]
+    achieved = SWEEP_BYTES * G / (sweep_ms * 1e-3)
+    traffic = traffic_from_profiles(G)
+    roofline = {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
+                "algorithmic_bytes_per_launch": SWEEP_BYTES * G,
+                "avg_launch_ms": sweep_ms,
+                "step_frac": main_res["agent_steps_per_s"] * STEP_BYTES / HBM_PEAK}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline")
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    out = {
+        "metric": "agent-steps/s batched vs plain at 5k/50k agents; p50/p99 step latency",
+        "value": main_res["agent_steps_per_s"],
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"flock5k x{args.envs} batched: {args.envs} envs x 5,000 agents, "
+                               "side 316, vision 8, 16 sectors, seeded uniform actions",
+                   "envs": args.envs, "agents": G, "graph_steps": K},
+        "batched": main_res,
+        **extra,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

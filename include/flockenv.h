@@ -177,6 +177,18 @@ int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward
 int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs,
                   float *reward, void *stream);
 
+/* Capture (or re-capture) the graph env_batch_run would replay for these
+ * arguments, without launching it.  Same arguments and errors. */
+int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs,
+                      float *reward, void *stream);
+
+/* One env_step_batched whose four phases are bracketed by HIP events on
+ * `stream`: phase_ms[0] move + cell count, [1] scan, [2] scatter, [3]
+ * neighbour sweep (milliseconds).  Synchronises the stream.  For
+ * profiling; results are the same as env_step_batched. */
+int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *reward,
+                           void *stream, float *phase_ms);
+
 /* --------------------------------------------------------------- policy */
 
 /* Shared policy network of Sec. 4.3/5: in -> hidden -> hidden -> 2, tanh on

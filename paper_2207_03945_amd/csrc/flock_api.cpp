@@ -18,13 +18,18 @@ using namespace flock;
 namespace {
 thread_local std::string g_err;
 
-int fail(int code, const char *fmt, ...) {
+int vfail(int code, const char *fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    g_err = buf;
+    return code;
+}
+
+int fail(int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vfail(code, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -37,7 +42,7 @@ bool finite(float v) { return isfinite(v) != 0; }
 // Largest agent count per env and per batch (row indices are int32).
 constexpr int64_t kMaxAgents = int64_t(1) << 26;
 constexpr int64_t kMaxBatchAgents = int64_t(1) << 30;
-// The two-level scan covers (16384 cells per tile) x (16384 tiles).
+// Cell indices are int32 and the two-level scan's tile count must fit a grid.
 constexpr int64_t kMaxBatchCells = int64_t(1) << 28;
 
 int check_params(const env_params_t *p) {
@@ -144,6 +149,14 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+int flock::set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(code, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
 // ------------------------------------------------------------------ objects
 
 struct flock_env {
@@ -174,7 +187,43 @@ struct flock_batch {
     StepPlan plan;
     bool uploaded = false;
     GraphCache gc;
+    hipEvent_t events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
+
+namespace flock {
+
+int validate_params(const env_params_t *p) { return check_params(p); }
+
+DevEnv env_descriptor(const env_t *env) { return env->desc; }
+
+int64_t env_cell_count(const env_t *env) { return (int64_t)env->gm.ncell * env->gm.ncell; }
+
+const env_params_t &env_params(const env_t *env) { return env->p; }
+
+int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
+                        const float *s_, hipStream_t s) {
+    const size_t b = (size_t)env->p.n_agents * sizeof(float);
+    if (b == 0) {
+        env->has_state = true;
+        return ENV_OK;
+    }
+    hipError_t e = hipMemcpyAsync(env->lay.x, x, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.y, y, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.th, th, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.s, s_, b, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+    env->has_state = true;
+    return ENV_OK;
+}
+
+size_t sort_scratch_bytes(int64_t G, int64_t C, int E) {
+    Carver cv{nullptr, 0};
+    SortArrays a;
+    carve_sort(cv, G, C, E, &a);
+    return align_up(cv.off, 256);
+}
+
+}  // namespace flock
 
 extern "C" {
 
@@ -398,6 +447,8 @@ void env_batch_destroy(env_batch_t *b) {
     if (!b) return;
     if (b->gc.exec) (void)hipGraphExecDestroy(b->gc.exec);
     if (b->gc.graph) (void)hipGraphDestroy(b->gc.graph);
+    for (auto &ev : b->events)
+        if (ev) (void)hipEventDestroy(ev);
     delete b;
 }
 
@@ -431,49 +482,99 @@ int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward
     return ENV_OK;
 }
 
-int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
-                  void *stream) {
+int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *reward,
+                           void *stream, float *phase_ms) {
+    if (!b || !phase_ms) return fail(ENV_EINVAL, "NULL argument");
+    if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    hipStream_t s = as_stream(stream);
+    int rc = batch_prepare(b, s);
+    if (rc != ENV_OK) return rc;
+    if (!b->events[0]) {
+        for (auto &ev : b->events) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+    }
+    for (int k = 0; k < 4; ++k) phase_ms[k] = 0.0f;
+    if (b->plan.G == 0) return ENV_OK;
+    hipError_t e = launch_step(b->plan, 1, act, obs, reward, 1, s, b->events);
+    if (e == hipSuccess) e = hipEventSynchronize(b->events[4]);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = hipEventElapsedTime(&phase_ms[k], b->events[k], b->events[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "env_step_batched_timed");
+    return ENV_OK;
+}
+
+static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs,
+                         float *reward, void *stream) {
     if (!b) return fail(ENV_EINVAL, "batch is NULL");
     if (k_steps < 1) return fail(ENV_EINVAL, "k_steps must be >= 1");
-    if (!stream) return fail(ENV_EINVAL, "env_batch_run needs a non-null stream (graph capture)");
+    if (!stream) return fail(ENV_EINVAL, "graph capture needs a non-null stream");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
     hipStream_t s = as_stream(stream);
     int rc = batch_prepare(b, s);
     if (rc != ENV_OK) return rc;
     GraphCache &gc = b->gc;
-    if (!gc.exec || gc.k != k_steps || gc.act != act || gc.obs != obs || gc.reward != reward ||
-        gc.stream != s) {
-        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
-        if (gc.graph) (void)hipGraphDestroy(gc.graph);
-        gc = GraphCache{};
-        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        const int64_t G = b->plan.G;
-        hipError_t le = hipSuccess;
-        for (int k = 0; k < k_steps && le == hipSuccess; ++k)
-            le = launch_step(b->plan, 1, act + (size_t)k * G * 2, obs, reward + (size_t)k * G, 1, s);
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(s, &graph);
-        if (le != hipSuccess || e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return hip_fail(le != hipSuccess ? le : e, "graph capture");
-        }
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        gc.exec = exec;
-        gc.graph = graph;
-        gc.k = k_steps;
-        gc.act = act;
-        gc.obs = obs;
-        gc.reward = reward;
-        gc.stream = s;
+    if (gc.exec && gc.k == k_steps && gc.act == act && gc.obs == obs && gc.reward == reward &&
+        gc.stream == s)
+        return ENV_OK;
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+    gc = GraphCache{};
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const int64_t G = b->plan.G;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < k_steps && le == hipSuccess; ++k)
+        le = launch_step(b->plan, 1, act + (size_t)k * G * 2, obs, reward + (size_t)k * G, 1, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : e, "graph capture");
     }
-    hipError_t e = hipGraphLaunch(gc.exec, s);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    gc.exec = exec;
+    gc.graph = graph;
+    gc.k = k_steps;
+    gc.act = act;
+    gc.obs = obs;
+    gc.reward = reward;
+    gc.stream = s;
+    return ENV_OK;
+}
+
+int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
+                      void *stream) {
+    return batch_capture(b, k_steps, act, obs, reward, stream);
+}
+
+int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
+                  void *stream) {
+    int rc = batch_capture(b, k_steps, act, obs, reward, stream);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = hipGraphLaunch(b->gc.exec, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return ENV_OK;
+}
+
+int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
+                    void *stream) {
+    if (!b || !pol) return fail(ENV_EINVAL, "batch or policy is NULL");
+    if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    if (policy_in_dim(pol) != b->plan.v)
+        return fail(ENV_EINVAL, "policy input %d != sectors %d", policy_in_dim(pol), b->plan.v);
+    hipStream_t s = as_stream(stream);
+    int rc = batch_prepare(b, s);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = policy_launch(pol, obs, b->plan.G, act, s);
+    if (e == hipSuccess) e = launch_step(b->plan, 1, act, obs, reward, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "env_step_policy");
     return ENV_OK;
 }
 

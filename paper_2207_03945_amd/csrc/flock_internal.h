@@ -13,11 +13,16 @@ namespace flock {
 constexpr float kTwoPiF = 6.28318548202514648438f;  // (float)(2 pi)
 constexpr int kBlock = 256;                           // threads per block (4 wave64)
 
-// Per-environment descriptor read by every kernel (device memory, 128 B).
+// Per-environment descriptor read by every kernel (device memory).
 struct DevEnv {
     float *x, *y, *th, *s;  // state, FP32 [n]
     double *ret;            // FP64 returns [n]
     int32_t *nb, *col;      // counts [n] (nullptr when not kept)
+    // Env-owned I/O rows, used when a launch gets no batch-wide arrays
+    // (serving: rows move between batches as requests come and go).
+    float *act;             // [n][2]
+    float *obs;             // [n][v]
+    float *rew;             // [n]
     int32_t n;              // agents
     int32_t agent_base;     // first row of this env in batch-wide arrays
     int32_t cell_base;      // first cell of this env in the batch cell space
@@ -32,7 +37,7 @@ struct DevEnv {
     float max_turn, max_dspeed, s_min, s_max;
     float sec_scale;        // FP32(v / 2pi)
 };
-static_assert(sizeof(DevEnv) <= 128, "DevEnv grew");
+static_assert(sizeof(DevEnv) <= 160, "DevEnv grew");
 
 // Device arrays of one cell-list sort over G agents and C cells.
 struct SortArrays {
@@ -85,9 +90,11 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 // Zero count and ticket (used once after carving).
 hipError_t launch_clear(const StepPlan &p, hipStream_t s);
 // Full step; do_move = 0 senses the current state without moving (reset).
-// act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]).
+// act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]); when NULL the
+// kernels use each env's own act/obs/rew rows from its descriptor.
 hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *obs,
-                       float *reward, int add_return, hipStream_t s);
+                       float *reward, int add_return, hipStream_t s,
+                       hipEvent_t *phase_events = nullptr);
 // Copy state in or out of one env.
 hipError_t launch_copy_state(const float *sx, const float *sy, const float *sth,
                              const float *ss, float *dx, float *dy, float *dth, float *ds,
@@ -96,16 +103,27 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 
-// Policy network ----------------------------------------------------------
-struct PolicyDev {
-    const uint16_t *w1;  // BF16 [hidden][in_pad]   (transposed: out-major)
-    const uint16_t *w2;  // BF16 [hidden][hidden]   (out-major)
-    const float *w3;     // FP32 [2][hidden]        (out-major)
-    const float *b1, *b2, *b3;
-    int in_dim, hidden;
-    float max_turn, max_dspeed;
-};
-hipError_t launch_policy(const PolicyDev &pol, const float *obs, int64_t n, float *act,
-                         hipStream_t s);
+// Policy network (policy_mfma.hip) ---------------------------------------------
+// act[n][2] = policy(obs[n][in_dim]) on `s`.
+hipError_t policy_launch(const pol_t *pol, const float *obs, int64_t n, float *act, hipStream_t s);
+// Over every row of a batch plan, reading obs and writing act through each
+// env's own rows (DevEnv::obs / DevEnv::act).
+hipError_t policy_launch_envs(const pol_t *pol, const StepPlan &plan, hipStream_t s);
+int policy_in_dim(const pol_t *pol);
+
+// Env internals used by the serving loop (flock_api.cpp) ---------------------
+int validate_params(const env_params_t *p);     // ENV_OK or ENV_EINVAL (+ message)
+DevEnv env_descriptor(const env_t *env);        // agent_base / cell_base are 0
+int64_t env_cell_count(const env_t *env);       // cells of this env's grid
+const env_params_t &env_params(const env_t *env);
+// Copy a host state into the env (async on s; host arrays must outlive the copy).
+int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
+                        const float *s_, hipStream_t s);
+// Bytes of the batch sort scratch for G agents, C cells, E envs.
+size_t sort_scratch_bytes(int64_t G, int64_t C, int E);
+
+// Error channel shared by every C entry point (flock_api.cpp): records a
+// thread-local message for env_last_error() and returns `code`.
+int set_error(int code, const char *fmt, ...);
 
 }  // namespace flock

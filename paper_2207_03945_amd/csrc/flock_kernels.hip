@@ -26,8 +26,12 @@
 //     lies in the far half of the box, where the shift is exact, so dx and
 //     dy carry a single rounding; d^2 = dx*dx + dy*dy (no FMA); the radius
 //     tests are strict;
-//   * the bearing comes from rotating (dx, dy) into the heading frame and a
-//     FP32 atan2, so it is within about 2e-6 rad of the exact bearing.
+//   * the bearing comes from rotating (dx, dy) into the heading frame,
+//     folding into the first octant and an odd polynomial for atan fitted
+//     here (max error 3.4e-7 rad); with the FP32 roundings the sector
+//     position is within about 1.5e-6 rad of the exact bearing.  It is
+//     evaluated for every candidate without a branch; only the per-sector
+//     minimum update is predicated on the pair being a neighbour.
 #include "flock_internal.h"
 
 namespace flock {
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, int n_envs,
 
     float x = E.x[i], y = E.y[i], h = E.th[i], sp = E.s[i];
     if (do_move) {
-        const float2 av = act[g];
+        const float2 av = act ? act[g] : reinterpret_cast<const float2 *>(E.act)[i];
         const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
         const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
         h = h + turn;
@@ -182,23 +186,29 @@ __global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ c
     if (t == 0) start[C] = total;
 }
 
-// Large C, phase 1: per-tile sums; the last tile to finish scans the sums.
-__global__ __launch_bounds__(kScanNT) void k_scan_reduce(const int32_t *__restrict__ count,
-                                                         int32_t *__restrict__ part,
-                                                         uint32_t *__restrict__ ticket,
-                                                         int32_t *__restrict__ start, int C) {
-    __shared__ int s_wave[kScanNT / 64 + 1];
+// Large C: tiles of kTile2 cells, one 256-thread block each.
+constexpr int kScan2NT = 256;
+constexpr int kScan2Items = 8;
+constexpr int kTile2 = kScan2NT * kScan2Items;
+
+// Phase 1: per-tile sums; the last tile to finish turns the sums into
+// exclusive tile offsets (in chunks of kTile2 with a running carry).
+__global__ __launch_bounds__(kScan2NT) void k_scan_reduce(const int32_t *__restrict__ count,
+                                                          int32_t *__restrict__ part,
+                                                          uint32_t *__restrict__ ticket,
+                                                          int32_t *__restrict__ start, int C) {
+    __shared__ int s_wave[kScan2NT / 64 + 1];
     __shared__ int s_last;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t base = (int64_t)blockIdx.x * kTile2;
     int sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t idx = base + k * kScanNT + t;
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t idx = base + k * kScan2NT + t;
         sum += idx < C ? count[idx] : 0;
     }
     int total;
-    (void)block_exclusive_scan<kScanNT>(sum, s_wave, &total);
+    (void)block_exclusive_scan<kScan2NT>(sum, s_wave, &total);
     if (t == 0) {
         part[blockIdx.x] = total;
         __threadfence();
@@ -208,65 +218,69 @@ __global__ __launch_bounds__(kScanNT) void k_scan_reduce(const int32_t *__restri
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    // Last block: exclusive scan of the per-tile sums, kScanItems per thread.
-    const int nb = gridDim.x;  // <= kScanTile (checked on the host)
-    int vals[kScanItems];
-    int psum = 0;
+    const int nb = gridDim.x;
+    int carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kTile2) {
+        int vals[kScan2Items];
+        int psum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int idx = t * kScanItems + k;
-        vals[k] = idx < nb ? __atomic_load_n(&part[idx], __ATOMIC_RELAXED) : 0;
-        psum += vals[k];
-    }
-    __syncthreads();
-    int grand;
-    int run = block_exclusive_scan<kScanNT>(psum, s_wave, &grand);
+        for (int k = 0; k < kScan2Items; ++k) {
+            const int idx = c0 + t * kScan2Items + k;
+            vals[k] = idx < nb ? __atomic_load_n(&part[idx], __ATOMIC_RELAXED) : 0;
+            psum += vals[k];
+        }
+        __syncthreads();
+        int chunk;
+        int run = block_exclusive_scan<kScan2NT>(psum, s_wave, &chunk) + carry;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int idx = t * kScanItems + k;
-        if (idx < nb) part[idx] = run;
-        run += vals[k];
+        for (int k = 0; k < kScan2Items; ++k) {
+            const int idx = c0 + t * kScan2Items + k;
+            if (idx < nb) part[idx] = run;
+            run += vals[k];
+        }
+        carry += chunk;
+        __syncthreads();
     }
     if (t == 0) {
-        start[C] = grand;
+        start[C] = carry;
         *ticket = 0u;
     }
 }
 
-// Large C, phase 2: scan each tile with its offset; re-zero the counts.
-__global__ __launch_bounds__(kScanNT) void k_scan_down(int32_t *__restrict__ count,
-                                                       const int32_t *__restrict__ part,
-                                                       int32_t *__restrict__ start, int C) {
-    __shared__ int s_wave[kScanNT / 64 + 1];
-    __shared__ int s_tile[kScanTile];
+// Phase 2: scan each tile with its offset; re-zero the counts.
+__global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ count,
+                                                        const int32_t *__restrict__ part,
+                                                        int32_t *__restrict__ start, int C) {
+    __shared__ int s_wave[kScan2NT / 64 + 1];
+    __shared__ int s_tile[kTile2];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t base = (int64_t)blockIdx.x * kTile2;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t idx = base + k * kScanNT + t;
-        s_tile[k * kScanNT + t] = idx < C ? count[idx] : 0;
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t idx = base + k * kScan2NT + t;
+        s_tile[k * kScan2NT + t] = idx < C ? count[idx] : 0;
     }
     __syncthreads();
-    int vals[kScanItems];
+    int vals[kScan2Items];
     int sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        vals[k] = s_tile[t * kScanItems + k];
+    for (int k = 0; k < kScan2Items; ++k) {
+        vals[k] = s_tile[t * kScan2Items + k];
         sum += vals[k];
     }
     int total;
-    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total) + part[blockIdx.x];
+    int run = block_exclusive_scan<kScan2NT>(sum, s_wave, &total) + part[blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        s_tile[t * kScanItems + k] = run;
+    for (int k = 0; k < kScan2Items; ++k) {
+        s_tile[t * kScan2Items + k] = run;
         run += vals[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t idx = base + k * kScanNT + t;
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t idx = base + k * kScan2NT + t;
         if (idx < C) {
-            start[idx] = s_tile[k * kScanNT + t];
+            start[idx] = s_tile[k * kScan2NT + t];
             count[idx] = 0;
         }
     }
@@ -290,32 +304,70 @@ struct PairAcc {
     int nb, col;
 };
 
+// Per-agent constants of the pair test.
+struct PairConst {
+    float r2, c2;   // radius^2, collide^2
+    float c, s;     // cos / sin of the agent's heading
+    float vf;       // sectors as float
+    int v;
+};
+
+// atan(t) / (2 pi) for t in [0, 1] as t * P(t^2); least-squares fit with
+// minimax reweighting on Chebyshev nodes, max error 5.4e-8 turns.
+__device__ __forceinline__ float atan_turns01(float t) {
+    const float t2 = t * t;
+    float p = 0.0010841276962310076f;
+    p = __builtin_fmaf(t2, p, -0.005348269362002611f);
+    p = __builtin_fmaf(t2, p, 0.012672491371631622f);
+    p = __builtin_fmaf(t2, p, -0.02106151357293129f);
+    p = __builtin_fmaf(t2, p, 0.03152511641383171f);
+    p = __builtin_fmaf(t2, p, -0.0530262365937233f);
+    p = __builtin_fmaf(t2, p, 0.15915432572364807f);
+    return p * t;
+}
+
+// Sector of the bearing of (dx, dy) relative to the heading (c, s): sector 0
+// starts at the heading, sectors run counter-clockwise; (0, 0) -> sector 0.
+__device__ __forceinline__ int sector_of(float dx, float dy, const PairConst &K) {
+    const float u = __builtin_fmaf(dx, K.c, dy * K.s);      // along the heading
+    const float w = __builtin_fmaf(dy, K.c, -(dx * K.s));   // to its left
+    const float au = fabsf(u), aw = fabsf(w);
+    const float mx = fmaxf(au, aw), mn = fminf(au, aw);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    float a = atan_turns01(t);
+    a = aw > au ? 0.25f - a : a;
+    a = u < 0.0f ? 0.5f - a : a;
+    a = w < 0.0f ? 1.0f - a : a;
+    const int k = (int)(a * K.vf);
+    return k < K.v - 1 ? k : K.v - 1;
+}
+
+template <int NT>
+__device__ __forceinline__ void pair_test(float dx, float dy, bool other, const PairConst &K,
+                                          uint32_t *smin, PairAcc &acc) {
+    const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+    const bool nbr = other && d2 < K.r2;
+    acc.nb += nbr ? 1 : 0;
+    acc.col += (nbr && d2 < K.c2) ? 1 : 0;
+    const int k = sector_of(dx, dy, K);
+    if (nbr) atomicMin(&smin[k * NT], __float_as_uint(d2));
+}
+
 // Test candidates [q0, q1) of cell order against agent p.  (offx, xi) and
 // (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis.
 template <int NT>
 __device__ __forceinline__ void sweep_run(const float2 *__restrict__ sxy, int q0, int q1, int p,
-                                          float offx, float xi, float offy, float yi, float r2,
-                                          float c2, float cth, float sth, float sec_scale, int v,
-                                          uint32_t *smin, PairAcc &acc) {
-    for (int q = q0; q < q1; ++q) {
-        const float2 pj = sxy[q];
-        const float dx = (pj.x + offx) - xi;
-        const float dy = (pj.y + offy) - yi;
-        const float d2 = dx * dx + dy * dy;
-        if (d2 < r2 && q != p) {
-            acc.nb += 1;
-            acc.col += d2 < c2 ? 1 : 0;
-            int k = 0;
-            if (d2 > 0.0f) {
-                const float u = dx * cth + dy * sth;
-                const float w = dy * cth - dx * sth;
-                float phi = atan2f(w, u);
-                if (phi < 0.0f) phi = phi + kTwoPiF;
-                k = (int)(phi * sec_scale);
-                k = k < v - 1 ? k : v - 1;
-            }
-            atomicMin(&smin[k * NT], __float_as_uint(d2));
-        }
+                                          float offx, float xi, float offy, float yi,
+                                          const PairConst &K, uint32_t *smin, PairAcc &acc) {
+    int q = q0;
+    for (; q + 1 < q1; q += 2) {
+        const float2 a = sxy[q], b = sxy[q + 1];
+        pair_test<NT>((a.x + offx) - xi, (a.y + offy) - yi, q != p, K, smin, acc);
+        pair_test<NT>((b.x + offx) - xi, (b.y + offy) - yi, q + 1 != p, K, smin, acc);
+    }
+    if (q < q1) {
+        const float2 a = sxy[q];
+        pair_test<NT>((a.x + offx) - xi, (a.y + offy) - yi, q != p, K, smin, acc);
     }
 }
 
@@ -349,32 +401,17 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, i
 
     const float2 me = a.sxy[p];
     const float2 cs = a.scs[p];
-    const float L = E.box, r2 = E.r2, c2 = E.c2, sec = E.sec_scale;
+    const float L = E.box;
     const int ncell = E.ncell, cb = E.cell_base;
+    const PairConst K{E.r2, E.c2, cs.x, cs.y, (float)v, v};
     PairAcc acc{0, 0};
 
     if (ncell == 1) {
         const int q0 = a.start[cb], q1 = a.start[cb + 1];
         for (int q = q0; q < q1; ++q) {
-            if (q == p) continue;
             const float2 pj = a.sxy[q];
-            const float dx = min_image_delta(pj.x, me.x, L);
-            const float dy = min_image_delta(pj.y, me.y, L);
-            const float d2 = dx * dx + dy * dy;
-            if (d2 < r2) {
-                acc.nb += 1;
-                acc.col += d2 < c2 ? 1 : 0;
-                int k = 0;
-                if (d2 > 0.0f) {
-                    const float u = dx * cs.x + dy * cs.y;
-                    const float w = dy * cs.x - dx * cs.y;
-                    float phi = atan2f(w, u);
-                    if (phi < 0.0f) phi = phi + kTwoPiF;
-                    k = (int)(phi * sec);
-                    k = k < v - 1 ? k : v - 1;
-                }
-                atomicMin(&smin[k * NT], __float_as_uint(d2));
-            }
+            pair_test<NT>(min_image_delta(pj.x, me.x, L), min_image_delta(pj.y, me.y, L), q != p, K,
+                          smin, acc);
         }
     } else {
         const int reach = E.reach;
@@ -394,17 +431,17 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, i
             const int colb = cb + ccx * ncell;
             if (lo < 0) {
                 sweep_run<NT>(a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell], p, offx, xi,
-                          -L, me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                          -L, me.y, K, smin, acc);
                 sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi + 1], p, offx, xi, 0.0f, me.y,
-                          r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                          K, smin, acc);
             } else if (hi >= ncell) {
                 sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + ncell], p, offx, xi, 0.0f,
-                          me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                          me.y, K, smin, acc);
                 sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi - ncell + 1], p, offx, xi, 0.0f,
-                          me.y - L, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                          me.y - L, K, smin, acc);
             } else {
                 sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + hi + 1], p, offx, xi, 0.0f,
-                          me.y, r2, c2, cs.x, cs.y, sec, v, smin, acc);
+                          me.y, K, smin, acc);
             }
         }
     }
@@ -412,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, i
     const int g = a.perm[p];
     const int i = g - E.agent_base;
     const float R = E.radius;
-    float *orow = obs + (size_t)g * v;
+    float *orow = obs ? obs + (size_t)g * v : E.obs + (size_t)i * v;
     if ((v & 3) == 0) {
         for (int k = 0; k < v; k += 4) {
             float o[4];
@@ -431,6 +468,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, i
     }
     const float r = E.r_nb * (float)acc.nb + E.r_col * (float)acc.col;
     if (reward) reward[g] = r;
+    else if (E.rew) E.rew[i] = r;
     if (add_ret) E.ret[i] += (double)r;
     if (E.nb) {
         E.nb[i] = acc.nb;
@@ -475,7 +513,7 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) /
 
 }  // namespace
 
-int scan_blocks_for(int64_t C) { return C <= kScanTile ? 0 : (int)((C + kScanTile - 1) / kScanTile); }
+int scan_blocks_for(int64_t C) { return C <= kScanTile ? 0 : (int)((C + kTile2 - 1) / kTile2); }
 
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     const int nb = scan_blocks_for(C);
@@ -501,21 +539,25 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
 }
 
 hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *obs,
-                       float *reward, int add_return, hipStream_t s) {
+                       float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
     if (p.G == 0) return hipSuccess;
     const int G = (int)p.G, C = (int)p.C;
     const unsigned nb = blocks_for(G, kBlock);
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, p.n_envs, G, do_move,
                        reinterpret_cast<const float2 *>(act));
+    if (ev) (void)hipEventRecord(ev[1], s);
     if (p.scan_blocks == 0) {
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanNT), 0, s, p.a.count, p.a.start, C);
     } else {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScanNT), 0, s, p.a.count,
+        hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
                            p.a.part, p.a.ticket, p.a.start, C);
-        hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScanNT), 0, s, p.a.count,
+        hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
                            p.a.part, p.a.start, C);
     }
+    if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, G);
+    if (ev) (void)hipEventRecord(ev[3], s);
     if (p.v <= 32) {
         const size_t lds = (size_t)p.v * 256 * sizeof(uint32_t);
         hipLaunchKernelGGL(k_sweep<256>, dim3(blocks_for(G, 256)), dim3(256), lds, s, p.a,
@@ -525,6 +567,7 @@ hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *
         hipLaunchKernelGGL(k_sweep<64>, dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a, p.n_envs,
                            G, p.v, obs, reward, add_return);
     }
+    if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }
 

@@ -1,0 +1,330 @@
+// policy_mfma.hip -- the shared policy network on gfx950 matrix cores.
+//
+// Sec. 4.3 of arXiv:2207.03945: one policy shared by every agent, each agent
+// an independent learner, so the batch axis is the agent axis; Sec. 5: two
+// hidden layers of 64 units.  Here: in -> 64 -> 64 -> 2, tanh after every
+// layer, the two outputs scaled to the turn / speed-change ranges of Sec. 4.1.
+//
+// Precision: inputs and weights rounded once to BF16 (round to nearest even),
+// products accumulated in FP32 by v_mfma_f32_32x32x16_bf16, biases and the
+// 64 -> 2 output layer in FP32 on the vector ALUs (with BF16-rounded weights).
+//
+// Layout.  One wave handles 32 agents per tile and computes the transposed
+// products H1^T = W1^T X^T and H2^T = W2^T H1^T (hidden units as MFMA rows,
+// agents as columns).  A 32x32 accumulator gives lane l the agent l % 32 and,
+// in register r, the hidden row 8 (r / 4) + 4 (l / 32) + r % 4.  Those eight
+// rows per lane group are exactly what the next product's B operand needs
+// once the reduction (K) order is permuted to match, so layer-1 results feed
+// layer 2 straight from registers; the permutation is applied to the weights
+// once on the host (pol_create).
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "flock_internal.h"
+
+namespace flock {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int kHidden = 64;
+constexpr int kPolBlock = 256;
+
+// Device workspace of one policy.
+struct PolLayout {
+    bf16x8 *w1f;  // [kc1][2 tiles][64 lanes]  A operand of layer 1
+    bf16x8 *w2f;  // [2 tiles][4 chunks][64 lanes]  A operand of layer 2
+    float *b1l;   // [2 tiles][2 groups][16]  bias per accumulator register
+    float *b2l;   // [2][2][16]
+    float *w3l;   // [2 outputs][2 tiles][2 groups][16]
+    float *b3;    // [2]
+    size_t bytes;
+};
+
+PolLayout carve_pol(char *base, int kc1) {
+    PolLayout l;
+    Carver cv{base, 0};
+    l.w1f = cv.take<bf16x8>((size_t)kc1 * 2 * 64);
+    l.w2f = cv.take<bf16x8>(2 * 4 * 64);
+    l.b1l = cv.take<float>(64);
+    l.b2l = cv.take<float>(64);
+    l.w3l = cv.take<float>(128);
+    l.b3 = cv.take<float>(2);
+    l.bytes = align_up(cv.off, 256);
+    return l;
+}
+
+// Hidden row held in accumulator register r by lane group g of a 32-row tile.
+inline int acc_row(int r, int g) { return 8 * (r / 4) + 4 * g + (r % 4); }
+
+__device__ __forceinline__ float tanh_fast(float x) {
+    x = fminf(fmaxf(x, -15.0f), 15.0f);
+    const float e = __expf(2.0f * x);
+    return __fdividef(e - 1.0f, e + 1.0f);
+}
+
+// Last env e with base[e] <= row.
+__device__ __forceinline__ int env_of_row(const int32_t *base, int n_envs, int64_t row) {
+    int lo = 0, hi = n_envs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Rows are agents; obs/act are [n][in_dim] / [n][2] arrays, or, when `envs`
+// is non-null, each row's env-owned rows found through the batch tables.
+__global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
+                                                      float max_turn, float max_dspeed,
+                                                      const float *__restrict__ obs, int64_t n,
+                                                      float2 *__restrict__ act,
+                                                      const DevEnv *__restrict__ envs,
+                                                      const int32_t *__restrict__ base, int n_envs) {
+    __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
+    for (int i = threadIdx.x; i < 64; i += kPolBlock) {
+        s_b1[i] = P.b1l[i];
+        s_b2[i] = P.b2l[i];
+    }
+    for (int i = threadIdx.x; i < 128; i += kPolBlock) s_w3[i] = P.w3l[i];
+    if (threadIdx.x < 2) s_b3[threadIdx.x] = P.b3[threadIdx.x];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    bf16x8 w1[2][2];
+    for (int kc = 0; kc < 2; ++kc)
+        for (int t = 0; t < 2; ++t)
+            w1[kc][t] = kc < kc1 ? P.w1f[(kc * 2 + t) * 64 + lane] : bf16x8{};
+    bf16x8 w2[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w2[t][c] = P.w2f[(t * 4 + c) * 64 + lane];
+
+    const int64_t waves = (int64_t)gridDim.x * (kPolBlock / 64);
+    const int64_t tiles = (n + 31) / 32;
+    for (int64_t tile = (int64_t)blockIdx.x * (kPolBlock / 64) + threadIdx.x / 64; tile < tiles;
+         tile += waves) {
+        const int64_t agent = tile * 32 + col;
+        const bool valid = agent < n;
+        const float *orow = obs + agent * in_dim;
+        float2 *arow = act + agent;
+        if (envs && valid) {
+            const DevEnv &E = envs[env_of_row(base, n_envs, agent)];
+            const int64_t i = agent - E.agent_base;
+            orow = E.obs + i * in_dim;
+            arow = reinterpret_cast<float2 *>(E.act) + i;
+        }
+        f32x16 acc1[2] = {f32x16{}, f32x16{}};
+        for (int kc = 0; kc < kc1; ++kc) {
+            bf16x8 xb;
+            const int k0 = 16 * kc + 8 * g;
+            if (valid && in_dim % 8 == 0 && k0 + 8 <= in_dim) {
+                const float4 *src = reinterpret_cast<const float4 *>(orow + k0);
+                const float4 u = src[0], w = src[1];
+                xb[0] = (__bf16)u.x; xb[1] = (__bf16)u.y; xb[2] = (__bf16)u.z; xb[3] = (__bf16)u.w;
+                xb[4] = (__bf16)w.x; xb[5] = (__bf16)w.y; xb[6] = (__bf16)w.z; xb[7] = (__bf16)w.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = k0 + j;
+                    xb[j] = (__bf16)((valid && k < in_dim) ? orow[k] : 0.0f);
+                }
+            }
+            acc1[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[kc][0], xb, acc1[0], 0, 0, 0);
+            acc1[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[kc][1], xb, acc1[1], 0, 0, 0);
+        }
+        // bias + tanh; registers 8 (c % 2) .. + 8 of tile c / 2 are chunk c of layer 2's K
+        bf16x8 h1[4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                h1[t * 2 + r / 8][r % 8] = (__bf16)tanh_fast(acc1[t][r] + s_b1[(t * 2 + g) * 16 + r]);
+        f32x16 acc2[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2[t][c], h1[c], acc2[t], 0, 0, 0);
+        float z0 = 0.0f, z1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float h = tanh_fast(acc2[t][r] + s_b2[(t * 2 + g) * 16 + r]);
+                z0 = z0 + h * s_w3[((0 * 2 + t) * 2 + g) * 16 + r];
+                z1 = z1 + h * s_w3[((1 * 2 + t) * 2 + g) * 16 + r];
+            }
+        z0 = z0 + __shfl_xor(z0, 32, 64);
+        z1 = z1 + __shfl_xor(z1, 32, 64);
+        if (g == 0 && valid)
+            *arow = make_float2(max_turn * tanhf(z0 + s_b3[0]), max_dspeed * tanhf(z1 + s_b3[1]));
+    }
+}
+
+uint16_t bf16_bits_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_round(float f) {
+    uint32_t u = (uint32_t)bf16_bits_rne(f) << 16;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+}  // namespace
+
+}  // namespace flock
+
+using namespace flock;
+
+struct flock_policy {
+    int in_dim, kc1;
+    float max_turn, max_dspeed;
+    PolLayout lay;
+    std::vector<char> host;  // staged device image, kept until pol_destroy
+};
+
+namespace flock {
+
+hipError_t policy_launch(const pol_t *p, const float *obs, int64_t n, float *act, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay, p->in_dim,
+                       p->kc1, p->max_turn, p->max_dspeed, obs, n, reinterpret_cast<float2 *>(act),
+                       nullptr, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, hipStream_t s) {
+    const int64_t n = plan.G;
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay, p->in_dim,
+                       p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr, plan.a.envs,
+                       plan.a.base, plan.n_envs);
+    return hipGetLastError();
+}
+
+int policy_in_dim(const pol_t *p) { return p->in_dim; }
+
+}  // namespace flock
+
+extern "C" {
+
+size_t pol_workspace_bytes(int in_dim, int hidden) {
+    if (in_dim < 1 || in_dim > 32 || hidden != kHidden) {
+        set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= 32 and hidden == 64");
+        return 0;
+    }
+    return carve_pol(nullptr, (in_dim + 15) / 16).bytes;
+}
+
+int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max_dspeed, void *ws,
+               size_t bytes, void *stream, pol_t **out) {
+    if (!w || !ws || !out) return set_error(ENV_EINVAL, "NULL argument to pol_create");
+    if (in_dim < 1 || in_dim > 32 || hidden != kHidden)
+        return set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= 32 and hidden == 64");
+    if (!(max_turn >= 0.0f) || !(max_dspeed >= 0.0f) || !isfinite(max_turn) || !isfinite(max_dspeed))
+        return set_error(ENV_EINVAL, "action scales must be finite and >= 0");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return set_error(ENV_EINVAL, "workspace must be 256-byte aligned");
+    const int H = kHidden;
+    const int kc1 = (in_dim + 15) / 16;
+    const size_t need = carve_pol(nullptr, kc1).bytes;
+    if (bytes < need)
+        return set_error(ENV_ENOMEM, "policy workspace has %zu bytes, needs %zu", bytes, need);
+    pol_t *p = new pol_t;
+    p->in_dim = in_dim;
+    p->kc1 = kc1;
+    p->max_turn = max_turn;
+    p->max_dspeed = max_dspeed;
+    p->lay = carve_pol(static_cast<char *>(ws), kc1);
+    const PolLayout &off = p->lay;
+    p->host.assign(need, 0);
+    char *hb = p->host.data();
+    // host image of the workspace: same offsets from the base as the device arrays
+    auto at = [&](const void *dev) {
+        return hb + (static_cast<const char *>(dev) - static_cast<const char *>(ws));
+    };
+    const float *W1 = w;
+    const float *b1 = W1 + in_dim * H;
+    const float *W2 = b1 + H;
+    const float *b2 = W2 + H * H;
+    const float *W3 = b2 + H;
+    const float *b3 = W3 + H * 2;
+    // layer-1 A operand: lane (g, col), element j = W1[16 kc + 8 g + j][32 t + col]
+    uint16_t *w1f = reinterpret_cast<uint16_t *>(at(off.w1f));
+    for (int kc = 0; kc < kc1; ++kc)
+        for (int t = 0; t < 2; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int g = lane / 32, col = lane % 32;
+                    const int k = 16 * kc + 8 * g + j, m = 32 * t + col;
+                    const float v = k < in_dim ? W1[k * H + m] : 0.0f;
+                    w1f[((kc * 2 + t) * 64 + lane) * 8 + j] = bf16_bits_rne(v);
+                }
+    // layer-2 A operand with the K order of layer 1's accumulator registers:
+    // chunk c, slot (g, j) <-> hidden unit 16 c + 8 (j / 4) + 4 g + j % 4
+    uint16_t *w2f = reinterpret_cast<uint16_t *>(at(off.w2f));
+    for (int t = 0; t < 2; ++t)
+        for (int c = 0; c < 4; ++c)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int g = lane / 32, col = lane % 32;
+                    const int hid = 16 * c + 8 * (j / 4) + 4 * g + (j % 4);
+                    w2f[((t * 4 + c) * 64 + lane) * 8 + j] = bf16_bits_rne(W2[hid * H + 32 * t + col]);
+                }
+    float *b1l = reinterpret_cast<float *>(at(off.b1l));
+    float *b2l = reinterpret_cast<float *>(at(off.b2l));
+    float *w3l = reinterpret_cast<float *>(at(off.w3l));
+    for (int t = 0; t < 2; ++t)
+        for (int g = 0; g < 2; ++g)
+            for (int r = 0; r < 16; ++r) {
+                const int h = 32 * t + acc_row(r, g);
+                b1l[(t * 2 + g) * 16 + r] = b1[h];
+                b2l[(t * 2 + g) * 16 + r] = b2[h];
+                for (int o = 0; o < 2; ++o)
+                    w3l[((o * 2 + t) * 2 + g) * 16 + r] = bf16_round(W3[h * 2 + o]);
+            }
+    float *b3d = reinterpret_cast<float *>(at(off.b3));
+    b3d[0] = b3[0];
+    b3d[1] = b3[1];
+    hipError_t e = hipMemcpyAsync(ws, hb, need, hipMemcpyHostToDevice,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        delete p;
+        return set_error(ENV_EHIP, "pol_create upload: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return ENV_OK;
+}
+
+void pol_destroy(pol_t *p) { delete p; }
+
+int pol_forward(pol_t *p, const float *obs, int64_t n, float *act, void *stream) {
+    if (!p) return set_error(ENV_EINVAL, "policy is NULL");
+    if (n < 0) return set_error(ENV_EINVAL, "n < 0");
+    if (n > 0 && (!obs || !act)) return set_error(ENV_EINVAL, "obs/act is NULL");
+    hipError_t e = policy_launch(p, obs, n, act, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(ENV_EHIP, "pol_forward: %s", hipGetErrorString(e));
+    return ENV_OK;
+}
+
+}  // extern "C"

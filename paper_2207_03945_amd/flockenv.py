@@ -93,6 +93,9 @@ def lib():
         "env_batch_offsets": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
         "env_step_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_batch_run": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+        "env_batch_capture": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+        "env_step_batched_timed": (ctypes.c_int, [_P, _P, _P, _P, _P,
+                                                  ctypes.POINTER(ctypes.c_float)]),
         "pol_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
         "pol_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                                       ctypes.c_float, _P, ctypes.c_size_t, _P, _PP]),
@@ -258,6 +261,24 @@ class Batch:
         _dev_f32(reward, (self.n,), "reward")
         check(lib().env_step_batched(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
 
+    def step_timed(self, act, obs, reward, stream=None):
+        """One step; returns (move, scan, scatter, sweep) durations in ms (HIP events)."""
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        ms = (ctypes.c_float * 4)()
+        check(lib().env_step_batched_timed(self.handle, _ptr(act), _ptr(obs), _ptr(reward),
+                                           _stream(stream), ms))
+        return tuple(ms)
+
+    def capture(self, k_steps, act, obs, reward, stream):
+        """Capture the k-step graph ``run`` replays, without launching it."""
+        _dev_f32(act, (k_steps, self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(reward, (k_steps, self.n), "reward")
+        check(lib().env_batch_capture(self.handle, k_steps, _ptr(act), _ptr(obs), _ptr(reward),
+                                      _stream(stream)))
+
     def run(self, k_steps, act, obs, reward, stream):
         """k_steps steps replayed from a HIP graph; ``stream`` must not be the null stream."""
         _dev_f32(act, (k_steps, self.n, 2), "act")
@@ -315,3 +336,68 @@ class Policy:
         _dev_f32(act, (n, 2), "act")
         check(lib().pol_forward(self.handle, _ptr(obs), n, _ptr(act), _stream(stream)))
         return act
+
+
+def request_bytes(params: Params) -> int:
+    """Arena bytes one serving request with these parameters occupies (0 if invalid)."""
+    return int(lib().srv_request_bytes(ctypes.byref(params.c())))
+
+
+class Server:
+    """Continuous-batching episode server (srv_* of the C ABI).
+
+    ``arena_bytes`` of device memory (a torch tensor) is the HBM budget the
+    server admits requests against.  Requests share ``policy``.
+    """
+
+    QUEUED, RUNNING, FINISHED = 0, 1, 2
+
+    def __init__(self, policy: Policy, arena_bytes: int, max_slots: int = 64, device="cuda",
+                 stream=None):
+        self.policy = policy
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = ctypes.c_void_p()
+        check(lib().srv_create(self.arena.data_ptr(), int(arena_bytes), int(max_slots),
+                               policy.handle, _stream(self.stream), ctypes.byref(h)))
+        self.handle = h
+        self.sizes = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.srv_destroy(h)
+            self.handle = None
+
+    def submit(self, params: Params, state, steps: int):
+        """Queue a request; returns (id, admitted_now).  ``state`` = host (x, y, th, s)."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in state]
+        for a in arrs:
+            if a.shape != (params.n_agents,):
+                raise ValueError("state arrays must have shape (n_agents,)")
+        rid = ctypes.c_int64()
+        rc = lib().srv_submit(self.handle, ctypes.byref(params.c()), *[a.ctypes.data for a in arrs],
+                              int(steps), ctypes.byref(rid))
+        if rc not in (ENV_OK, ENV_EAGAIN):
+            check(rc)
+        self.sizes[rid.value] = params.n_agents
+        return rid.value, rc == ENV_OK
+
+    def tick(self):
+        """One serving tick; returns (requests stepped, agents stepped)."""
+        n, a = ctypes.c_int32(), ctypes.c_int64()
+        check(lib().srv_tick(self.handle, ctypes.byref(n), ctypes.byref(a)))
+        return n.value, a.value
+
+    def poll(self, rid: int):
+        st, done = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().srv_poll(self.handle, int(rid), ctypes.byref(st), ctypes.byref(done)))
+        return st.value, done.value
+
+    def result(self, rid: int):
+        import numpy as np
+        n = self.sizes.pop(rid)
+        out = np.zeros(n, np.float64)
+        check(lib().srv_result(self.handle, int(rid), out.ctypes.data if n else None, n))
+        return out

@@ -1,0 +1,107 @@
+"""GPU policy network (BF16 MFMA, FP32 accumulate) against the FP64 oracle.
+
+Error bound.  With u = 2^-9 (half an ulp of BF16, relative) every input,
+weight and layer-1 activation carries a relative rounding of at most u, and
+FP32 accumulation adds at most K * 2^-24 relative.  Propagating first-order
+absolute errors through z = W^T h + b (tanh is 1-Lipschitz) gives, per agent
+and unit, with dh the error of the layer input (its own BF16 rounding
+included),
+    |dz| <= |W|^T dh + (u + K 2^-24) |W|^T |h| + 1e-6   (tanh evaluation)
+and the action error is at most scale * |dz_out|.  The test computes this
+bound in FP64 for every agent and requires the GPU error to stay under it.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+flock = pytest.importorskip("paper_2207_03945_amd")
+
+U_BF16 = 2.0 ** -9
+
+
+def error_bound(obs, ws, bs, scale=(0.2, 0.1)):
+    h = np.asarray(obs, np.float64)
+    dh = U_BF16 * np.abs(h)                  # input rounding
+    for layer, (w, b) in enumerate(zip(ws, bs)):
+        w = np.asarray(w, np.float64)
+        aw = np.abs(w)
+        k = w.shape[0]
+        dz = dh @ aw + (U_BF16 + k * 2.0 ** -24) * (np.abs(h) @ aw) + 1e-6
+        h = np.tanh(h @ w + b)
+        dh = dz + (U_BF16 * np.abs(h) if layer < len(ws) - 2 else 0.0)  # h1 re-rounded to BF16
+    return dh * np.asarray(scale)
+
+
+def make_policy(in_dim, seed=0):
+    ws, bs = workloads.xavier_weights([in_dim, 64, 64, 2], seed=seed)
+    bs = [b + np.float32(0.05) * (k + 1) for k, b in enumerate(bs)]  # non-zero biases
+    return flock.Policy(ws, bs), ws, bs
+
+
+@pytest.mark.parametrize("in_dim,n", [(16, 4096), (16, 1), (16, 77), (8, 1000), (20, 333), (32, 64)])
+def test_policy_matches_fp64_within_bound(in_dim, n):
+    pol, ws, bs = make_policy(in_dim)
+    g = np.random.default_rng(in_dim * 1000 + n)
+    obs = g.random((n, in_dim)).astype(np.float32)
+    obs[g.random((n, in_dim)) < 0.3] = 0.0          # empty sectors read 0
+    act = pol.forward(torch.from_numpy(obs).cuda())
+    torch.cuda.synchronize()
+    got = act.cpu().numpy().astype(np.float64)
+    ref = oracle.policy_forward(obs, ws, bs)
+    bound = error_bound(obs, ws, bs)
+    err = np.abs(got - ref)
+    assert (err <= bound).all(), f"max err {err.max():.3e}, bound at worst {bound[err > bound][:3]}"
+    print(f"in={in_dim} n={n}: max |act err| {err.max():.2e} (turn) / mean bound {bound.mean():.2e}")
+
+
+def test_policy_row_independent_bitwise():
+    """An agent's action does not depend on its tile or the batch size."""
+    pol, _, _ = make_policy(16)
+    g = np.random.default_rng(3)
+    obs = torch.from_numpy(g.random((1000, 16)).astype(np.float32)).cuda()
+    a_full = pol.forward(obs)
+    perm = torch.from_numpy(g.permutation(1000)).cuda()
+    a_perm = pol.forward(obs[perm].contiguous())
+    assert torch.equal(a_perm, a_full[perm])
+    a_part = pol.forward(obs[37:70].contiguous())
+    assert torch.equal(a_part, a_full[37:70])
+
+
+def test_policy_empty_input():
+    pol, _, _ = make_policy(16)
+    act = pol.forward(torch.empty(0, 16, device="cuda"))
+    torch.cuda.synchronize()
+    assert act.shape == (0, 2)
+
+
+def test_step_policy_equals_forward_then_step():
+    ns, boxes = [300, 1200, 64], [70.0, 140.0, 33.0]
+    pol, _, _ = make_policy(16)
+    envs_a, envs_b = [], []
+    for k, (n, b) in enumerate(zip(ns, boxes)):
+        st = workloads.uniform_state(n, b, seed=k)
+        for lst in (envs_a, envs_b):
+            e = flock.Env(flock.Params(n_agents=n, box=b, sectors=16))
+            e.set_state(*[torch.from_numpy(a).cuda() for a in st])
+            lst.append(e)
+    obs_a = torch.cat([e.reset() for e in envs_a]).contiguous()
+    obs_b = torch.cat([e.reset() for e in envs_b]).contiguous()
+    ba, bb = flock.Batch(envs_a), flock.Batch(envs_b)
+    G = ba.n
+    act_a = torch.empty(G, 2, device="cuda")
+    rew_a = torch.empty(G, device="cuda")
+    rew_b = torch.empty(G, device="cuda")
+    for t in range(5):
+        ba.step_policy(pol, act_a, obs_a, rew_a)
+        act_b = pol.forward(obs_b)
+        bb.step(act_b, obs_b, rew_b)
+        torch.cuda.synchronize()
+        assert torch.equal(act_a, act_b), t
+        assert torch.equal(obs_a, obs_b), t
+        assert torch.equal(rew_a, rew_b), t

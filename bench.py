@@ -139,6 +139,63 @@ def bench_plain(env, n, K, W, seed):
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
 
 
+def bench_serving(flock, workloads, duration, rate=20.0, lo=500, hi=50000, steps=200, seed=0,
+                  burst=48):
+    """Serving loop: Poisson arrivals of episode requests, one closed-loop step per tick.
+
+    Phase 1 replays `duration` seconds of Poisson arrivals (rate/s) in real
+    time; phase 2 submits `burst` requests at once (saturation).  Reports the
+    tick (= step) latency percentiles and agent-steps/s while busy.
+    """
+    import math
+    ws, bs = workloads.xavier_weights([V, 64, 64, 2], seed=0)
+    pol = flock.Policy(ws, bs)
+
+    def run(arrivals, sizes, boxes, env_offset):
+        srv = flock.Server(pol, 8 << 30, max_slots=64)
+        states = [workloads.uniform_state(int(n), float(b), seed=seed, env=env_offset + k)
+                  for k, (n, b) in enumerate(zip(sizes, boxes))]
+        ids, lat, agents, ticks, max_run = [], [], 0, 0, 0
+        i, t0, busy = 0, time.perf_counter(), 0.0
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(arrivals) and arrivals[i] <= now:
+                p = flock.Params(n_agents=int(sizes[i]), box=float(boxes[i]), sectors=V)
+                ids.append(srv.submit(p, states[i], steps)[0])
+                i += 1
+            ts = time.perf_counter()
+            n_run, ag = srv.tick()
+            te = time.perf_counter()
+            if n_run:
+                lat.append(te - ts)
+                busy += te - ts
+                agents += ag
+                ticks += 1
+                max_run = max(max_run, n_run)
+            elif i == len(arrivals):
+                if all(srv.poll(r)[0] == srv.FINISHED for r in ids):
+                    break
+            else:
+                time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        for r in ids:
+            srv.result(r)
+        return {"requests": len(ids), "ticks": ticks, "max_running": max_run,
+                "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                "agent_steps_per_s_busy": agents / busy if busy else 0.0,
+                "agent_steps_per_s_wall": agents / wall, "wall_s": wall}
+
+    arrivals = workloads.poisson_arrivals(rate, duration, seed)
+    sizes, boxes = workloads.uneven_env_sizes(len(arrivals), lo, hi, seed=seed + 1)
+    poisson = run(arrivals, sizes, boxes, 0)
+    bs_sizes, bs_boxes = workloads.uneven_env_sizes(burst, lo, hi, seed=seed + 2)
+    burst_res = run(np.zeros(burst), bs_sizes, bs_boxes, 10000)
+    return {"workload": f"Poisson arrivals {rate}/s for {duration} s, N log-uniform [{lo}, {hi}], "
+                        f"side 4 sqrt(N), {steps} steps each, fused BF16 policy; then a burst of "
+                        f"{burst} requests",
+            "poisson": poisson, "burst": burst_res}
+
+
 def cpu_baseline(seconds):
     """The oracle (all-pairs, FP64 view) on the host, 5,000-agent env, bounded sample."""
     import oracle
@@ -187,6 +244,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="skip the 50k and plain legs")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -228,6 +286,27 @@ def main():
             bat = bench_batched(flock, b50, K, W, seed=4, timed_reps=10)
             extra[name] = {"plain": plain, "batched_x20": bat}
             del b50, e50
+        log("[bench] uneven 256 envs")
+        ns, boxes = workloads.uneven_env_sizes(256, 100, 20000, seed=0)
+        states = [workloads.uniform_state(int(n), float(b), seed=0, env=k)
+                  for k, (n, b) in enumerate(zip(ns, boxes))]
+        plist = [flock.Params(n_agents=int(n), box=float(b), sectors=V) for n, b in zip(ns, boxes)]
+        from paper_2207_03945_amd import autotune
+        reach, tune_ms = autotune.tune_reach(plist, states, cache=None)
+        envs_u = []
+        for p_, st in zip(plist, states):
+            p_.cell_reach = reach
+            e = flock.Env(p_)
+            e.set_state(*[torch.from_numpy(a).cuda() for a in st])
+            e.reset()
+            envs_u.append(e)
+        bu = flock.Batch(envs_u)
+        extra["uneven256"] = {"agents": bu.n, "cell_reach": reach,
+                              "tuned_ms": {str(k): v for k, v in tune_ms.items()},
+                              **bench_batched(flock, bu, K, W, seed=5, timed_reps=10)}
+        del bu, envs_u
+        log("[bench] serving")
+        extra["serving"] = bench_serving(flock, workloads, args.serve_seconds)
     else:
         del envs
 

@@ -109,20 +109,22 @@ DevEnv make_desc(const env_params_t &p, const Geometry &gm) {
     d.inv_cell = gm.inv_cell;
     d.r2 = p.radius * p.radius;
     d.c2 = p.collide * p.collide;
-    d.radius = p.radius;
+    d.inv_radius = (float)(1.0 / (double)p.radius);
     d.r_nb = p.r_nb;
     d.r_col = p.r_col;
     d.max_turn = p.max_turn;
     d.max_dspeed = p.max_dspeed;
     d.s_min = p.s_min;
     d.s_max = p.s_max;
-    d.sec_scale = (float)((double)p.sectors / 6.283185307179586476925286766559);
     return d;
 }
 
+// Device arrays of one env: two cell-order record buffers (ping-pong), the
+// agent-order counts and the scratch of its own (batch-of-one) step.
 struct EnvLayout {
-    float *x, *y, *th, *s;
-    double *ret;
+    float4 *rec[2];
+    int32_t *id[2];
+    double *ret[2];
     int32_t *nb, *col;
     SortArrays sort;
     size_t bytes;
@@ -132,11 +134,11 @@ EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
     EnvLayout l;
     Carver cv{base, 0};
     const int64_t n = p.n_agents;
-    l.x = cv.take<float>(n);
-    l.y = cv.take<float>(n);
-    l.th = cv.take<float>(n);
-    l.s = cv.take<float>(n);
-    l.ret = cv.take<double>(n);
+    for (int b = 0; b < 2; ++b) {
+        l.rec[b] = cv.take<float4>(n);
+        l.id[b] = cv.take<int32_t>(n);
+        l.ret[b] = cv.take<double>(n);
+    }
     const bool counts = (p.flags & ENV_FLAG_COUNTS) != 0;
     l.nb = counts ? cv.take<int32_t>(n) : nullptr;
     l.col = counts ? cv.take<int32_t>(n) : nullptr;
@@ -163,12 +165,46 @@ struct flock_env {
     env_params_t p;
     Geometry gm;
     EnvLayout lay;
-    StepPlan plan;
-    DevEnv desc;          // host copy of this env's own descriptor
-    int32_t base_host[2]; // {0, n}
+    StepPlan plan;          // its own step: a batch of one
+    DevEnv scalars;         // descriptor without buffer pointers
+    DevEnv own[2];          // own tables: [b] has buffer b current
+    int32_t base_host[2];   // {0, n}
+    int parity = 0;         // index of the current record buffer
     bool has_state = false;
     bool reset_done = false;
+    bool uploaded = false;
 };
+
+namespace {
+
+DevEnv orient(const env_t *e, int cur) {
+    DevEnv d = e->scalars;
+    d.rec_cur = e->lay.rec[cur];
+    d.rec_nxt = e->lay.rec[cur ^ 1];
+    d.id_cur = e->lay.id[cur];
+    d.id_nxt = e->lay.id[cur ^ 1];
+    d.ret_cur = e->lay.ret[cur];
+    d.ret_nxt = e->lay.ret[cur ^ 1];
+    return d;
+}
+
+int upload_own(env_t *e, hipStream_t s) {
+    if (e->uploaded) return ENV_OK;
+    hipError_t err = hipMemcpyAsync(e->lay.sort.envs[0], &e->own[0], sizeof(DevEnv),
+                                    hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->lay.sort.envs[1], &e->own[1], sizeof(DevEnv),
+                             hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->lay.sort.base, e->base_host, sizeof(e->base_host),
+                             hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = launch_clear(e->plan, s);
+    if (err != hipSuccess) return hip_fail(err, "env descriptor upload");
+    e->uploaded = true;
+    return ENV_OK;
+}
+
+}  // namespace
 
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -181,12 +217,13 @@ struct GraphCache {
 
 struct flock_batch {
     std::vector<env_t *> envs;
-    std::vector<DevEnv> descs;
+    std::vector<int> base_par;       // env parities the tables were built for
+    std::vector<DevEnv> tab[2];      // [t]: env k has buffer base_par[k] ^ t current
     std::vector<int32_t> base;
     std::vector<int64_t> off;
     StepPlan plan;
     bool uploaded = false;
-    GraphCache gc;
+    GraphCache gc[2];                // graphs by starting table
     hipEvent_t events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -194,25 +231,40 @@ namespace flock {
 
 int validate_params(const env_params_t *p) { return check_params(p); }
 
-DevEnv env_descriptor(const env_t *env) { return env->desc; }
+DevEnv env_descriptor(const env_t *env, int flip) { return orient(env, env->parity ^ (flip & 1)); }
 
 int64_t env_cell_count(const env_t *env) { return (int64_t)env->gm.ncell * env->gm.ncell; }
 
 const env_params_t &env_params(const env_t *env) { return env->p; }
 
+int env_parity(const env_t *env) { return env->parity; }
+
+void env_advance(env_t *env, int steps) { env->parity ^= (steps & 1); }
+
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s) {
-    const size_t b = (size_t)env->p.n_agents * sizeof(float);
-    if (b == 0) {
-        env->has_state = true;
-        return ENV_OK;
-    }
-    hipError_t e = hipMemcpyAsync(env->lay.x, x, b, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.y, y, b, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.th, th, b, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(env->lay.s, s_, b, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "state upload");
+    const int n = env->p.n_agents;
     env->has_state = true;
+    if (n == 0) return ENV_OK;
+    // Stage the agent-order arrays in the next buffer's record area (free
+    // until the next step) and load them into the current buffer.
+    float *stage = reinterpret_cast<float *>(env->lay.rec[env->parity ^ 1]);
+    const size_t b = (size_t)n * sizeof(float);
+    hipError_t e = hipMemcpyAsync(stage, x, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(stage + n, y, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(stage + 2 * (size_t)n, th, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(stage + 3 * (size_t)n, s_, b, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_load_state(stage, stage + n, stage + 2 * (size_t)n, stage + 3 * (size_t)n,
+                              env->lay.rec[env->parity], env->lay.id[env->parity], n, s);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+    return ENV_OK;
+}
+
+int env_returns_to(env_t *env, double *out, hipStream_t s) {
+    hipError_t e = launch_store_returns(env->lay.ret[env->parity], env->lay.id[env->parity], out,
+                                        env->p.n_agents, s);
+    if (e != hipSuccess) return hip_fail(e, "returns");
     return ENV_OK;
 }
 
@@ -249,16 +301,11 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->p = *p;
     e->gm = gm;
     e->lay = carve_env(static_cast<char *>(workspace), *p, gm);
-    e->desc = make_desc(*p, gm);
-    e->desc.x = e->lay.x;
-    e->desc.y = e->lay.y;
-    e->desc.th = e->lay.th;
-    e->desc.s = e->lay.s;
-    e->desc.ret = e->lay.ret;
-    e->desc.nb = e->lay.nb;
-    e->desc.col = e->lay.col;
-    e->desc.agent_base = 0;
-    e->desc.cell_base = 0;
+    e->scalars = make_desc(*p, gm);
+    e->scalars.nb = e->lay.nb;
+    e->scalars.col = e->lay.col;
+    e->own[0] = orient(e, 0);
+    e->own[1] = orient(e, 1);
     e->base_host[0] = 0;
     e->base_host[1] = p->n_agents;
     e->plan.a = e->lay.sort;
@@ -266,7 +313,6 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.G = p->n_agents;
     e->plan.C = (int64_t)gm.ncell * gm.ncell;
     e->plan.v = p->sectors;
-    e->plan.flags = p->flags;
     e->plan.scan_blocks = scan_blocks_for(e->plan.C);
     *out = e;
     g_err.clear();
@@ -288,8 +334,8 @@ int env_set_state(env_t *env, const float *x, const float *y, const float *th, c
     if (!env) return fail(ENV_EINVAL, "env is NULL");
     const int n = env->p.n_agents;
     if (n > 0 && (!x || !y || !th || !s)) return fail(ENV_EINVAL, "state pointer is NULL");
-    hipError_t e = launch_copy_state(x, y, th, s, env->lay.x, env->lay.y, env->lay.th,
-                                     env->lay.s, n, as_stream(stream));
+    hipError_t e = launch_load_state(x, y, th, s, env->lay.rec[env->parity],
+                                     env->lay.id[env->parity], n, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_set_state");
     env->has_state = true;
     return ENV_OK;
@@ -300,8 +346,8 @@ int env_get_state(env_t *env, float *x, float *y, float *th, float *s, void *str
     const int n = env->p.n_agents;
     if (n > 0 && (!x || !y || !th || !s)) return fail(ENV_EINVAL, "state pointer is NULL");
     if (!env->has_state) return fail(ENV_ESTATE, "env has no state yet");
-    hipError_t e = launch_copy_state(env->lay.x, env->lay.y, env->lay.th, env->lay.s, x, y, th, s,
-                                     n, as_stream(stream));
+    hipError_t e = launch_store_state(env->lay.rec[env->parity], env->lay.id[env->parity], x, y,
+                                      th, s, n, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_get_state");
     return ENV_OK;
 }
@@ -312,20 +358,15 @@ int env_reset(env_t *env, float *obs, void *stream) {
     const int n = env->p.n_agents;
     if (n > 0 && !obs) return fail(ENV_EINVAL, "obs is NULL");
     hipStream_t s = as_stream(stream);
-    hipError_t e = hipMemcpyAsync(env->lay.sort.envs, &env->desc, sizeof(DevEnv),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "env_reset: descriptor upload");
-    e = hipMemcpyAsync(env->lay.sort.base, env->base_host, sizeof(env->base_host),
-                       hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "env_reset: base upload");
-    e = launch_clear(env->plan, s);
-    if (e != hipSuccess) return hip_fail(e, "env_reset: clear");
-    e = launch_zero_f64(env->lay.ret, n, s);
+    int rc = upload_own(env, s);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = launch_zero_f64(env->lay.ret[env->parity], n, s);
     if (e != hipSuccess) return hip_fail(e, "env_reset: zero returns");
     // The sense-only pass yields no reward: the episode's first reward comes
-    // with the first step.
-    e = launch_step(env->plan, 0, nullptr, obs, nullptr, 0, s);
+    // with the first step.  It sorts the records into cell order.
+    e = launch_step(env->plan, env->parity, 0, nullptr, obs, nullptr, 0, s);
     if (e != hipSuccess) return hip_fail(e, "env_reset: sense");
+    if (n > 0) env->parity ^= 1;
     env->reset_done = true;
     return ENV_OK;
 }
@@ -335,8 +376,9 @@ int env_step(env_t *env, const float *act, float *obs, float *reward, void *stre
     if (!env->reset_done) return fail(ENV_ESTATE, "env_step before env_reset");
     const int n = env->p.n_agents;
     if (n > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
-    hipError_t e = launch_step(env->plan, 1, act, obs, reward, 1, as_stream(stream));
+    hipError_t e = launch_step(env->plan, env->parity, 1, act, obs, reward, 1, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_step");
+    if (n > 0) env->parity ^= 1;
     return ENV_OK;
 }
 
@@ -357,16 +399,13 @@ int env_get_returns(env_t *env, double *ret, void *stream) {
     if (!env->reset_done) return fail(ENV_ESTATE, "env_get_returns before env_reset");
     const int n = env->p.n_agents;
     if (n > 0 && !ret) return fail(ENV_EINVAL, "ret is NULL");
-    hipError_t e = launch_copy_f64(env->lay.ret, ret, n, as_stream(stream));
-    if (e != hipSuccess) return hip_fail(e, "env_get_returns");
-    return ENV_OK;
+    return env_returns_to(env, ret, as_stream(stream));
 }
 
 // ------------------------------------------------------------------- batch
 
-static int batch_layout(env_t *const *envs, int n_envs, std::vector<DevEnv> *descs,
-                        std::vector<int32_t> *base, std::vector<int64_t> *off, int64_t *G,
-                        int64_t *C, int *v) {
+static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *base,
+                        std::vector<int64_t> *off, int64_t *G, int64_t *C, int *v) {
     if (!envs || n_envs < 1) return fail(ENV_EINVAL, "need at least one env");
     int64_t g = 0, c = 0;
     for (int k = 0; k < n_envs; ++k) {
@@ -375,12 +414,6 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<DevEnv> *des
         if (e->p.sectors != envs[0]->p.sectors)
             return fail(ENV_EINVAL, "env %d has %d sectors, env 0 has %d", k, e->p.sectors,
                         envs[0]->p.sectors);
-        if (descs) {
-            DevEnv d = e->desc;
-            d.agent_base = (int32_t)g;
-            d.cell_base = (int32_t)c;
-            descs->push_back(d);
-        }
         if (base) base->push_back((int32_t)g);
         if (off) off->push_back(g);
         g += e->p.n_agents;
@@ -399,11 +432,8 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<DevEnv> *des
 size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs) {
     int64_t G, C;
     int v;
-    if (batch_layout(envs, n_envs, nullptr, nullptr, nullptr, &G, &C, &v) != ENV_OK) return 0;
-    Carver cv{nullptr, 0};
-    SortArrays a;
-    carve_sort(cv, G, C, n_envs, &a);
-    return align_up(cv.off, 256);
+    if (batch_layout(envs, n_envs, nullptr, nullptr, &G, &C, &v) != ENV_OK) return 0;
+    return sort_scratch_bytes(G, C, n_envs);
 }
 
 int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env_batch_t **out) {
@@ -414,7 +444,7 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     env_batch_t *b = new env_batch_t;
     int64_t G, C;
     int v;
-    int rc = batch_layout(envs, n_envs, &b->descs, &b->base, &b->off, &G, &C, &v);
+    int rc = batch_layout(envs, n_envs, &b->base, &b->off, &G, &C, &v);
     if (rc != ENV_OK) {
         delete b;
         return rc;
@@ -433,20 +463,27 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
                     align_up(cv.off, 256));
     }
     b->envs.assign(envs, envs + n_envs);
+    b->base_par.assign(n_envs, -1);
     b->plan.n_envs = n_envs;
     b->plan.G = G;
     b->plan.C = C;
     b->plan.v = v;
-    b->plan.flags = 0;
     b->plan.scan_blocks = scan_blocks_for(C);
     *out = b;
     return ENV_OK;
 }
 
+static void drop_graphs(env_batch_t *b) {
+    for (auto &gc : b->gc) {
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+        if (gc.graph) (void)hipGraphDestroy(gc.graph);
+        gc = GraphCache{};
+    }
+}
+
 void env_batch_destroy(env_batch_t *b) {
     if (!b) return;
-    if (b->gc.exec) (void)hipGraphExecDestroy(b->gc.exec);
-    if (b->gc.graph) (void)hipGraphDestroy(b->gc.graph);
+    drop_graphs(b);
     for (auto &ev : b->events)
         if (ev) (void)hipEventDestroy(ev);
     delete b;
@@ -458,27 +495,64 @@ int env_batch_offsets(const env_batch_t *b, int64_t *off) {
     return ENV_OK;
 }
 
-static int batch_prepare(env_batch_t *b, hipStream_t s) {
-    if (b->uploaded) return ENV_OK;
-    hipError_t e = hipMemcpyAsync(b->plan.a.envs, b->descs.data(), b->descs.size() * sizeof(DevEnv),
-                                  hipMemcpyHostToDevice, s);
+// Make the device tables match the envs' current buffers; *table receives the
+// table index of the next step.
+static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
+    const int E = (int)b->envs.size();
+    bool consistent = b->uploaded;
+    const int t = b->envs[0]->parity ^ b->base_par[0];
+    for (int k = 0; k < E && consistent; ++k)
+        consistent = (b->envs[k]->parity ^ b->base_par[k]) == t;
+    if (consistent) {
+        *table = t & 1;
+        return ENV_OK;
+    }
+    for (int f = 0; f < 2; ++f) {
+        b->tab[f].clear();
+        for (int k = 0; k < E; ++k) {
+            DevEnv d = orient(b->envs[k], b->envs[k]->parity ^ f);
+            d.agent_base = b->base[k];
+            d.cell_base = 0;
+            b->tab[f].push_back(d);
+        }
+    }
+    int64_t c = 0;
+    for (int k = 0; k < E; ++k) {
+        b->tab[0][k].cell_base = b->tab[1][k].cell_base = (int32_t)c;
+        c += (int64_t)b->envs[k]->gm.ncell * b->envs[k]->gm.ncell;
+        b->base_par[k] = b->envs[k]->parity;
+    }
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 2 && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(b->plan.a.envs[f], b->tab[f].data(), E * sizeof(DevEnv),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->plan.a.base, b->base.data(), b->base.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_clear(b->plan, s);
+    if (e == hipSuccess && !b->uploaded) e = launch_clear(b->plan, s);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
     b->uploaded = true;
+    drop_graphs(b);
+    *table = 0;
     return ENV_OK;
+}
+
+// Every env of the batch swapped buffers `steps` times (empty envs too, so
+// the parities of a batch stay in step).
+static void batch_advance(env_batch_t *b, int steps) {
+    for (env_t *e : b->envs) e->parity ^= (steps & 1);
 }
 
 int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward, void *stream) {
     if (!b) return fail(ENV_EINVAL, "batch is NULL");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
     hipStream_t s = as_stream(stream);
-    int rc = batch_prepare(b, s);
+    int t;
+    int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
-    hipError_t e = launch_step(b->plan, 1, act, obs, reward, 1, s);
+    hipError_t e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_batched");
+    batch_advance(b, 1);
     return ENV_OK;
 }
 
@@ -487,7 +561,8 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
     if (!b || !phase_ms) return fail(ENV_EINVAL, "NULL argument");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
     hipStream_t s = as_stream(stream);
-    int rc = batch_prepare(b, s);
+    int t;
+    int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
     if (!b->events[0]) {
         for (auto &ev : b->events) {
@@ -497,8 +572,10 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
     }
     for (int k = 0; k < 4; ++k) phase_ms[k] = 0.0f;
     if (b->plan.G == 0) return ENV_OK;
-    hipError_t e = launch_step(b->plan, 1, act, obs, reward, 1, s, b->events);
-    if (e == hipSuccess) e = hipEventSynchronize(b->events[4]);
+    hipError_t e = launch_step(b->plan, t, 1, act, obs, reward, 1, s, b->events);
+    if (e != hipSuccess) return hip_fail(e, "env_step_batched_timed");
+    batch_advance(b, 1);
+    e = hipEventSynchronize(b->events[4]);
     for (int k = 0; k < 4 && e == hipSuccess; ++k)
         e = hipEventElapsedTime(&phase_ms[k], b->events[k], b->events[k + 1]);
     if (e != hipSuccess) return hip_fail(e, "env_step_batched_timed");
@@ -506,15 +583,17 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
 }
 
 static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs,
-                         float *reward, void *stream) {
+                         float *reward, void *stream, int *table) {
     if (!b) return fail(ENV_EINVAL, "batch is NULL");
     if (k_steps < 1) return fail(ENV_EINVAL, "k_steps must be >= 1");
     if (!stream) return fail(ENV_EINVAL, "graph capture needs a non-null stream");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
     hipStream_t s = as_stream(stream);
-    int rc = batch_prepare(b, s);
+    int t;
+    int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
-    GraphCache &gc = b->gc;
+    *table = t;
+    GraphCache &gc = b->gc[t];
     if (gc.exec && gc.k == k_steps && gc.act == act && gc.obs == obs && gc.reward == reward &&
         gc.stream == s)
         return ENV_OK;
@@ -526,7 +605,8 @@ static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *o
     const int64_t G = b->plan.G;
     hipError_t le = hipSuccess;
     for (int k = 0; k < k_steps && le == hipSuccess; ++k)
-        le = launch_step(b->plan, 1, act + (size_t)k * G * 2, obs, reward + (size_t)k * G, 1, s);
+        le = launch_step(b->plan, t ^ (k & 1), 1, act + (size_t)k * G * 2, obs,
+                         reward + (size_t)k * G, 1, s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -551,15 +631,18 @@ static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *o
 
 int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
                       void *stream) {
-    return batch_capture(b, k_steps, act, obs, reward, stream);
+    int t;
+    return batch_capture(b, k_steps, act, obs, reward, stream, &t);
 }
 
 int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
                   void *stream) {
-    int rc = batch_capture(b, k_steps, act, obs, reward, stream);
+    int t;
+    int rc = batch_capture(b, k_steps, act, obs, reward, stream, &t);
     if (rc != ENV_OK) return rc;
-    hipError_t e = hipGraphLaunch(b->gc.exec, as_stream(stream));
+    hipError_t e = hipGraphLaunch(b->gc[t].exec, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    batch_advance(b, k_steps);
     return ENV_OK;
 }
 
@@ -570,11 +653,13 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
     if (policy_in_dim(pol) != b->plan.v)
         return fail(ENV_EINVAL, "policy input %d != sectors %d", policy_in_dim(pol), b->plan.v);
     hipStream_t s = as_stream(stream);
-    int rc = batch_prepare(b, s);
+    int t;
+    int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
     hipError_t e = policy_launch(pol, obs, b->plan.G, act, s);
-    if (e == hipSuccess) e = launch_step(b->plan, 1, act, obs, reward, 1, s);
+    if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_policy");
+    batch_advance(b, 1);
     return ENV_OK;
 }
 

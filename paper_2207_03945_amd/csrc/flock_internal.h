@@ -1,5 +1,6 @@
-// Internal declarations shared by the kernels (flock_kernels.hip) and the
-// C-ABI layer (flock_api.cpp).  Not part of the public ABI.
+// Internal declarations shared by the kernels (flock_kernels.hip), the C-ABI
+// layer (flock_api.cpp), the policy (policy_mfma.hip) and the server
+// (server.cpp).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,45 +15,50 @@ constexpr float kTwoPiF = 6.28318548202514648438f;  // (float)(2 pi)
 constexpr int kBlock = 256;                           // threads per block (4 wave64)
 
 // Per-environment descriptor read by every kernel (device memory).
+//
+// An env keeps its agents in CELL ORDER: record p of the current buffer is
+// the p-th agent of the env's last counting sort, and id[p] names that
+// agent (its row in agent-order arrays).  Each step reads the current
+// buffer and writes the next one in the new cell order (ping-pong), so every
+// per-agent access of the step is sequential except the agent-order
+// action read and view/reward write.
 struct DevEnv {
-    float *x, *y, *th, *s;  // state, FP32 [n]
-    double *ret;            // FP64 returns [n]
-    int32_t *nb, *col;      // counts [n] (nullptr when not kept)
-    // Env-owned I/O rows, used when a launch gets no batch-wide arrays
-    // (serving: rows move between batches as requests come and go).
-    float *act;             // [n][2]
-    float *obs;             // [n][v]
-    float *rew;             // [n]
-    int32_t n;              // agents
-    int32_t agent_base;     // first row of this env in batch-wide arrays
-    int32_t cell_base;      // first cell of this env in the batch cell space
-    int32_t ncell;          // cells per side (1 = all pairs)
-    int32_t reach;          // stencil half-width in cells (0 when ncell == 1)
-    float box;              // L
-    float inv_cell;         // FP32 multiplier: cell = floor(x * inv_cell)
-    float r2;               // radius^2 (FP32)
-    float c2;               // collide^2 (FP32)
-    float radius;
+    float4 *rec_cur, *rec_nxt;   // (x, y, heading, speed), FP32
+    int32_t *id_cur, *id_nxt;    // agent index within the env
+    double *ret_cur, *ret_nxt;   // FP64 returns
+    int32_t *nb, *col;           // agent-order counts (nullptr when not kept)
+    // Env-owned agent-order I/O rows, used when a launch gets no batch-wide
+    // arrays (serving: rows move between batches as requests come and go).
+    float *act;                  // [n][2]
+    float *obs;                  // [n][v]
+    float *rew;                  // [n]
+    int32_t n;                   // agents
+    int32_t agent_base;          // first row of this env in batch-wide arrays
+    int32_t cell_base;           // first cell of this env in the batch cell space
+    int32_t ncell;               // cells per side (1 = all pairs)
+    int32_t reach;               // stencil half-width in cells (0 when ncell == 1)
+    float box;                   // L
+    float inv_cell;              // FP32 multiplier: cell = floor(x * inv_cell)
+    float r2;                    // radius^2 (FP32)
+    float c2;                    // collide^2 (FP32)
+    float inv_radius;            // 1 / radius (FP32)
     float r_nb, r_col;
     float max_turn, max_dspeed, s_min, s_max;
-    float sec_scale;        // FP32(v / 2pi)
 };
-static_assert(sizeof(DevEnv) <= 160, "DevEnv grew");
+static_assert(sizeof(DevEnv) <= 192, "DevEnv grew");
 
-// Device arrays of one cell-list sort over G agents and C cells.
+// Device scratch of one counting sort over G agents and C cells.
 struct SortArrays {
-    int32_t *key;     // [G] global cell of each agent (row order)
-    int32_t *slot;    // [G] rank within its cell (arrival order of the atomic)
-    float4 *tmp;      // [G] (x', y', cos th', sin th') in row order
-    float2 *sxy;      // [G] positions in cell order
-    float2 *scs;      // [G] (cos, sin) of heading in cell order
-    int32_t *perm;    // [G] row of the agent at each cell-order position
-    int32_t *count;   // [C] agents per cell; zero between steps
-    int32_t *start;   // [C + 1] exclusive prefix of count
-    int32_t *part;    // [scan partials]
-    uint32_t *ticket; // [1] scan completion counter; zero between steps
-    DevEnv *envs;     // [E] descriptors
-    int32_t *base;    // [E + 1] agent_base of each env, then G
+    int32_t *key;      // [G] new global cell of record p
+    int32_t *slot;     // [G] rank of record p within its new cell
+    float4 *tmp;       // [G] moved record p (old order)
+    float2 *sxy;       // [G] positions in the new cell order (candidates)
+    int32_t *count;    // [C] agents per cell; zero between steps
+    int32_t *start;    // [C + 1] exclusive prefix of count
+    int32_t *part;     // [scan partials]
+    uint32_t *ticket;  // [1] scan completion counter; zero between steps
+    DevEnv *envs[2];   // [E] descriptor tables: [0] as stored, [1] buffers swapped
+    int32_t *base;     // [E + 1] agent_base of each env, then G
 };
 
 // Launch plan of one step over a fixed set of envs.
@@ -62,13 +68,14 @@ struct StepPlan {
     int64_t G;    // agents
     int64_t C;    // cells
     int v;        // sectors
-    int flags;
     int scan_blocks;  // 0 -> single-block scan
 };
 
 // Workspace carving --------------------------------------------------------
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Carves consecutive 256-byte-aligned arrays out of a base pointer; with a
+// null base it only accumulates the size (pointers stay null).
 struct Carver {
     char *base;
     size_t off;
@@ -83,44 +90,55 @@ struct Carver {
 
 // Number of scan partial blocks for C cells (0 = one block does everything).
 int scan_blocks_for(int64_t C);
-// Carve the sort arrays for G agents, C cells and E envs.
+// Carve the sort scratch for G agents, C cells and E envs.
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 
 // Launchers (return hipSuccess or the first error) ------------------------
 // Zero count and ticket (used once after carving).
 hipError_t launch_clear(const StepPlan &p, hipStream_t s);
-// Full step; do_move = 0 senses the current state without moving (reset).
+// One step with descriptor table `table` (0 or 1) of the plan.
+// do_move = 0 senses the current state without moving (episode start).
 // act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]); when NULL the
 // kernels use each env's own act/obs/rew rows from its descriptor.
-hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *obs,
+// add_return = 1 adds the reward to the FP64 returns.
+hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
                        float *reward, int add_return, hipStream_t s,
                        hipEvent_t *phase_events = nullptr);
-// Copy state in or out of one env.
-hipError_t launch_copy_state(const float *sx, const float *sy, const float *sth,
-                             const float *ss, float *dx, float *dy, float *dth, float *ds,
-                             int n, hipStream_t s);
+// Load an agent-order state into buffer `rec`/`id` (identity order).
+hipError_t launch_load_state(const float *x, const float *y, const float *th, const float *sp,
+                             float4 *rec, int32_t *id, int n, hipStream_t s);
+// Agent-order state / returns out of a cell-order buffer.
+hipError_t launch_store_state(const float4 *rec, const int32_t *id, float *x, float *y,
+                              float *th, float *sp, int n, hipStream_t s);
+hipError_t launch_store_returns(const double *ret, const int32_t *id, double *out, int n,
+                                hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
-hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+
+// Env internals used by the batch and serving layers (flock_api.cpp) -------
+int validate_params(const env_params_t *p);     // ENV_OK or ENV_EINVAL (+ message)
+// Descriptor with agent_base = cell_base = 0, oriented so that rec_cur is
+// the env's current buffer (flip = 1 swaps cur and nxt).
+DevEnv env_descriptor(const env_t *env, int flip);
+int64_t env_cell_count(const env_t *env);       // cells of this env's grid
+const env_params_t &env_params(const env_t *env);
+int env_parity(const env_t *env);
+void env_advance(env_t *env, int steps);        // record `steps` stepped elsewhere
+// Copy a host state into the env (async on s; host arrays must outlive the copy).
+int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
+                        const float *s_, hipStream_t s);
+// Device FP64 returns of the env in agent order, into `out` (device [n]).
+int env_returns_to(env_t *env, double *out, hipStream_t s);
+// Bytes of the batch sort scratch for G agents, C cells, E envs.
+size_t sort_scratch_bytes(int64_t G, int64_t C, int E);
 
 // Policy network (policy_mfma.hip) ---------------------------------------------
 // act[n][2] = policy(obs[n][in_dim]) on `s`.
 hipError_t policy_launch(const pol_t *pol, const float *obs, int64_t n, float *act, hipStream_t s);
 // Over every row of a batch plan, reading obs and writing act through each
-// env's own rows (DevEnv::obs / DevEnv::act).
-hipError_t policy_launch_envs(const pol_t *pol, const StepPlan &plan, hipStream_t s);
+// env's own rows (DevEnv::obs / DevEnv::act) of descriptor table `table`.
+hipError_t policy_launch_envs(const pol_t *pol, const StepPlan &plan, int table, hipStream_t s);
 int policy_in_dim(const pol_t *pol);
-
-// Env internals used by the serving loop (flock_api.cpp) ---------------------
-int validate_params(const env_params_t *p);     // ENV_OK or ENV_EINVAL (+ message)
-DevEnv env_descriptor(const env_t *env);        // agent_base / cell_base are 0
-int64_t env_cell_count(const env_t *env);       // cells of this env's grid
-const env_params_t &env_params(const env_t *env);
-// Copy a host state into the env (async on s; host arrays must outlive the copy).
-int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
-                        const float *s_, hipStream_t s);
-// Bytes of the batch sort scratch for G agents, C cells, E envs.
-size_t sort_scratch_bytes(int64_t G, int64_t C, int E);
 
 // Error channel shared by every C entry point (flock_api.cpp): records a
 // thread-local message for env_last_error() and returns `code`.

@@ -3,16 +3,22 @@
 // One step (Sec. 4.1 of arXiv:2207.03945: apply the actions, then update
 // view and reward over every pair in spatial proximity; Sec. 2.1: all agents
 // update simultaneously) is four dependent phases over a whole batch of
-// environments at once:
+// environments at once.  Agents are kept in cell order between steps (see
+// DevEnv), so every phase streams its per-agent data sequentially:
 //
-//   k_move_count  rotate/accelerate/move/wrap each agent (FP32), compute its
-//                 cell, and take a rank in that cell with one atomic add
+//   k_move_count  record p: rotate/accelerate/move/wrap (FP32), new cell key,
+//                 rank within the cell.  Records of a block were sorted by
+//                 their previous cell, so their new keys span a narrow range:
+//                 ranks come from an LDS histogram and one global atomic per
+//                 distinct key (global atomics per record as a fallback)
 //   k_scan_*      exclusive prefix of the per-cell counts (and re-zero them)
-//   k_scatter     counting-sort scatter: cell-ordered positions + headings
-//   k_sweep       one thread per agent in cell order walks the (2r+1)^2 cell
-//                 block round its own cell; per pair: periodic image, d^2,
-//                 radius tests, sector of the bearing, per-sector minimum in
-//                 LDS; then view, reward and the FP64 return
+//   k_scatter     record p -> its new cell-order position (ping-pong buffer),
+//                 with its agent id and FP64 return; positions for the sweep
+//   k_sweep       one lane per agent in the new cell order walks the cells of
+//                 its (2r+1)^2 block (runs of consecutive cells, read from
+//                 L2-resident sorted positions); per candidate: periodic
+//                 image, d^2, radius tests, sector of the bearing, per-sector
+//                 minimum in LDS; then view, reward and the FP64 return
 //
 // Envs of a batch live in one global cell space (env k's cells start at
 // cell_base), so one counting sort serves every env and the cell-order range
@@ -24,14 +30,15 @@
 //     state is the correctly rounded FP32 result of the stated operations;
 //   * pair displacement: the periodic shift is applied to whichever operand
 //     lies in the far half of the box, where the shift is exact, so dx and
-//     dy carry a single rounding; d^2 = dx*dx + dy*dy (no FMA); the radius
-//     tests are strict;
+//     dy carry a single rounding; d^2 = fma(dx, dx, dy*dy); the radius tests
+//     are strict;
 //   * the bearing comes from rotating (dx, dy) into the heading frame,
 //     folding into the first octant and an odd polynomial for atan fitted
 //     here (max error 3.4e-7 rad); with the FP32 roundings the sector
-//     position is within about 1.5e-6 rad of the exact bearing.  It is
-//     evaluated for every candidate without a branch; only the per-sector
-//     minimum update is predicated on the pair being a neighbour.
+//     position is within about 1.5e-6 rad of the exact bearing;
+//   * view: 1 - sqrt(d^2_min) * (1/R), within a few ulp of 1 - d_min/R.
+#include <limits.h>
+
 #include "flock_internal.h"
 
 namespace flock {
@@ -59,55 +66,99 @@ __device__ __forceinline__ int env_search(const int32_t *base, int n_envs, int r
     return lo;
 }
 
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+    return x;
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
+    return x;
+}
+
 // --------------------------------------------------------------------- move
 
-__global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, int n_envs, int G,
-                                                       int do_move, const float2 *__restrict__ act) {
-    __shared__ int s_env;
-    const int g0 = blockIdx.x * kBlock;
-    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, g0);
-    __syncthreads();
-    const int g = g0 + threadIdx.x;
-    if (g >= G) return;
-    int e = s_env;
-    while (a.base[e + 1] <= g) ++e;
-    const DevEnv &E = a.envs[e];
-    const int i = g - E.agent_base;
+constexpr int kHistBins = 2048;
 
-    float x = E.x[i], y = E.y[i], h = E.th[i], sp = E.s[i];
-    if (do_move) {
-        const float2 av = act ? act[g] : reinterpret_cast<const float2 *>(E.act)[i];
-        const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
-        const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
-        h = h + turn;
-        if (h < 0.0f) h = h + kTwoPiF;
-        if (h >= kTwoPiF) h = h - kTwoPiF;
-        sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+__global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEnv *__restrict__ envs,
+                                                       int n_envs, int G, int do_move,
+                                                       const float2 *__restrict__ act) {
+    __shared__ int s_env;
+    __shared__ int s_kmin[kBlock / 64], s_kmax[kBlock / 64];
+    __shared__ int s_hist[kHistBins];
+    const int p0 = blockIdx.x * kBlock;
+    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    __syncthreads();
+    const int p = p0 + threadIdx.x;
+    const bool live = p < G;
+    int key = 0;
+    if (live) {
+        int e = s_env;
+        while (a.base[e + 1] <= p) ++e;
+        const DevEnv &E = envs[e];
+        const int i = p - E.agent_base;
+        const float4 r = E.rec_cur[i];
+        float x = r.x, y = r.y, h = r.z, sp = r.w;
+        if (do_move) {
+            const int id = E.id_cur[i];
+            const float2 av =
+                act ? act[E.agent_base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+            const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
+            const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
+            h = h + turn;
+            if (h < 0.0f) h = h + kTwoPiF;
+            if (h >= kTwoPiF) h = h - kTwoPiF;
+            sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+            double sd, cd;
+            sincos((double)h, &sd, &cd);
+            const float c = (float)cd, sn = (float)sd;
+            const float L = E.box;
+            float nx = x + sp * c;
+            if (nx < 0.0f) nx = nx + L;
+            if (nx >= L) nx = nx - L;
+            float ny = y + sp * sn;
+            if (ny < 0.0f) ny = ny + L;
+            if (ny >= L) ny = ny - L;
+            x = nx;
+            y = ny;
+        }
+        a.tmp[p] = make_float4(x, y, h, sp);
+        key = E.cell_base + cell_of(x, E.inv_cell, E.ncell) * E.ncell + cell_of(y, E.inv_cell, E.ncell);
+        a.key[p] = key;
     }
-    double sd, cd;
-    sincos((double)h, &sd, &cd);
-    const float c = (float)cd, sn = (float)sd;
-    if (do_move) {
-        const float L = E.box;
-        float nx = x + sp * c;
-        if (nx < 0.0f) nx = nx + L;
-        if (nx >= L) nx = nx - L;
-        float ny = y + sp * sn;
-        if (ny < 0.0f) ny = ny + L;
-        if (ny >= L) ny = ny - L;
-        E.x[i] = nx;
-        E.y[i] = ny;
-        E.th[i] = h;
-        E.s[i] = sp;
-        x = nx;
-        y = ny;
+    // key range of the block
+    int kmin = wave_min(live ? key : INT_MAX);
+    int kmax = wave_max(live ? key : INT_MIN);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_kmin[wid] = kmin;
+        s_kmax[wid] = kmax;
     }
-    const int cx = cell_of(x, E.inv_cell, E.ncell);
-    const int cy = cell_of(y, E.inv_cell, E.ncell);
-    const int key = E.cell_base + cx * E.ncell + cy;
-    a.slot[g] = atomicAdd(&a.count[key], 1);
-    a.key[g] = key;
-    a.tmp[g] = make_float4(x, y, c, sn);
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        kmin = min(kmin, s_kmin[w]);
+        kmax = max(kmax, s_kmax[w]);
+    }
+    const int range = kmax - kmin;  // >= 0: every block holds at least one record
+    int slot = 0;
+    if (range < kHistBins) {
+        for (int b = threadIdx.x; b <= range; b += kBlock) s_hist[b] = 0;
+        __syncthreads();
+        const int lrank = live ? atomicAdd(&s_hist[key - kmin], 1) : 0;
+        __syncthreads();
+        for (int b = threadIdx.x; b <= range; b += kBlock) {
+            const int c = s_hist[b];
+            if (c) s_hist[b] = atomicAdd(&a.count[kmin + b], c);
+        }
+        __syncthreads();
+        slot = live ? s_hist[key - kmin] + lrank : 0;
+    } else if (live) {
+        slot = atomicAdd(&a.count[key], 1);
+    }
+    if (live) a.slot[p] = slot;
 }
 
 // --------------------------------------------------------------------- scan
@@ -143,25 +194,22 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
 
 constexpr int kScanNT = 1024;
 constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanNT * kScanItems;  // cells per scan block
+constexpr int kScanTile = kScanNT * kScanItems;  // cells of the single-block scan
 
 // C <= kScanTile: one block does the whole scan and re-zeroes the counts.
 __global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ count,
                                                          int32_t *__restrict__ start, int C) {
     __shared__ int s_wave[kScanNT / 64 + 1];
+    __shared__ int s_tile[kScanTile];
     const int t = threadIdx.x;
-    int vals[kScanItems];
-    int sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int idx = k * kScanNT + t;  // coalesced: item-major
-        vals[k] = idx < C ? count[idx] : 0;
+        s_tile[idx] = idx < C ? count[idx] : 0;
     }
-    // thread t owns cells t*kScanItems .. : transpose through LDS for order
-    __shared__ int s_tile[kScanTile];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) s_tile[k * kScanNT + t] = vals[k];
     __syncthreads();
+    int vals[kScanItems];
+    int sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         vals[k] = s_tile[t * kScanItems + k];
@@ -288,29 +336,28 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ co
 
 // ------------------------------------------------------------------ scatter
 
-__global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, int G) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= G) return;
-    const int pos = a.start[a.key[g]] + a.slot[g];
-    const float4 t = a.tmp[g];
-    a.sxy[pos] = make_float2(t.x, t.y);
-    a.scs[pos] = make_float2(t.z, t.w);
-    a.perm[pos] = g;
+__global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *__restrict__ envs,
+                                                    int n_envs, int G) {
+    __shared__ int s_env;
+    const int p0 = blockIdx.x * kBlock;
+    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    __syncthreads();
+    const int p = p0 + threadIdx.x;
+    if (p >= G) return;
+    int e = s_env;
+    while (a.base[e + 1] <= p) ++e;
+    const DevEnv &E = envs[e];
+    const int i = p - E.agent_base;
+    const int pos = a.start[a.key[p]] + a.slot[p];
+    const int j = pos - E.agent_base;
+    const float4 r = a.tmp[p];
+    E.rec_nxt[j] = r;
+    E.id_nxt[j] = E.id_cur[i];
+    E.ret_nxt[j] = E.ret_cur[i];
+    a.sxy[pos] = make_float2(r.x, r.y);
 }
 
 // -------------------------------------------------------------------- sweep
-
-struct PairAcc {
-    int nb, col;
-};
-
-// Per-agent constants of the pair test.
-struct PairConst {
-    float r2, c2;   // radius^2, collide^2
-    float c, s;     // cos / sin of the agent's heading
-    float vf;       // sectors as float
-    int v;
-};
 
 // atan(t) / (2 pi) for t in [0, 1] as t * P(t^2); least-squares fit with
 // minimax reweighting on Chebyshev nodes, max error 5.4e-8 turns.
@@ -328,9 +375,9 @@ __device__ __forceinline__ float atan_turns01(float t) {
 
 // Sector of the bearing of (dx, dy) relative to the heading (c, s): sector 0
 // starts at the heading, sectors run counter-clockwise; (0, 0) -> sector 0.
-__device__ __forceinline__ int sector_of(float dx, float dy, const PairConst &K) {
-    const float u = __builtin_fmaf(dx, K.c, dy * K.s);      // along the heading
-    const float w = __builtin_fmaf(dy, K.c, -(dx * K.s));   // to its left
+__device__ __forceinline__ int sector_of(float dx, float dy, float c, float s, float vf, int v) {
+    const float u = __builtin_fmaf(dx, c, dy * s);      // along the heading
+    const float w = __builtin_fmaf(dy, c, -(dx * s));   // to its left
     const float au = fabsf(u), aw = fabsf(w);
     const float mx = fmaxf(au, aw), mn = fminf(au, aw);
     const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
@@ -338,41 +385,12 @@ __device__ __forceinline__ int sector_of(float dx, float dy, const PairConst &K)
     a = aw > au ? 0.25f - a : a;
     a = u < 0.0f ? 0.5f - a : a;
     a = w < 0.0f ? 1.0f - a : a;
-    const int k = (int)(a * K.vf);
-    return k < K.v - 1 ? k : K.v - 1;
+    const int k = (int)(a * vf);
+    return k < v - 1 ? k : v - 1;
 }
 
-template <int NT>
-__device__ __forceinline__ void pair_test(float dx, float dy, bool other, const PairConst &K,
-                                          uint32_t *smin, PairAcc &acc) {
-    const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-    const bool nbr = other && d2 < K.r2;
-    acc.nb += nbr ? 1 : 0;
-    acc.col += (nbr && d2 < K.c2) ? 1 : 0;
-    const int k = sector_of(dx, dy, K);
-    if (nbr) atomicMin(&smin[k * NT], __float_as_uint(d2));
-}
-
-// Test candidates [q0, q1) of cell order against agent p.  (offx, xi) and
-// (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis.
-template <int NT>
-__device__ __forceinline__ void sweep_run(const float2 *__restrict__ sxy, int q0, int q1, int p,
-                                          float offx, float xi, float offy, float yi,
-                                          const PairConst &K, uint32_t *smin, PairAcc &acc) {
-    int q = q0;
-    for (; q + 1 < q1; q += 2) {
-        const float2 a = sxy[q], b = sxy[q + 1];
-        pair_test<NT>((a.x + offx) - xi, (a.y + offy) - yi, q != p, K, smin, acc);
-        pair_test<NT>((b.x + offx) - xi, (b.y + offy) - yi, q + 1 != p, K, smin, acc);
-    }
-    if (q < q1) {
-        const float2 a = sxy[q];
-        pair_test<NT>((a.x + offx) - xi, (a.y + offy) - yi, q != p, K, smin, acc);
-    }
-}
-
-// All-pairs run for single-cell envs: per candidate, shift the operand in the
-// far half of the box when the raw difference exceeds half the box.
+// Periodic displacement for single-cell (all-pairs) envs: the shift by L is
+// applied to whichever operand lies in the far half, where it is exact.
 __device__ __forceinline__ float min_image_delta(float xj, float xi, float L) {
     const float d = xj - xi;
     if (d > 0.5f * L) return (xj - L) - xi;
@@ -380,39 +398,79 @@ __device__ __forceinline__ float min_image_delta(float xj, float xi, float L) {
     return d;
 }
 
-// NT threads per block; the per-thread sector minima take v * NT * 4 bytes of LDS.
+// Test candidates [q, q1) against the lane's agent: distance test, and for a
+// neighbour the count, the collision count and the per-sector minimum (an
+// LDS atomic min on the lane's own slot).  The sector is computed for every
+// candidate (branch-free); only the LDS update is predicated.  (offx, xi),
+// (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis;
+// minimg selects the per-candidate minimum image (single-cell envs).
+template <int NT, int UNROLL>
+__device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
+                                          int q, int q1, int self, float offx, float xi,
+                                          float offy, float yi, bool minimg, float L, float r2,
+                                          float c2, float c, float s, float vf, int v, int &nb,
+                                          int &col) {
+    auto test = [&](const float2 pj, int qq) {
+        float dx, dy;
+        if (minimg) {
+            dx = min_image_delta(pj.x, xi, L);
+            dy = min_image_delta(pj.y, yi, L);
+        } else {
+            dx = (pj.x + offx) - xi;
+            dy = (pj.y + offy) - yi;
+        }
+        const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+        const bool nbr = d2 < r2 && qq != self;
+        nb += nbr ? 1 : 0;
+        col += (nbr && d2 < c2) ? 1 : 0;
+        const int k = sector_of(dx, dy, c, s, vf, v);
+        if (nbr) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+    };
+    for (; q + UNROLL <= q1; q += UNROLL) {
+        float2 pj[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) pj[u] = sxy[q + u];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) test(pj[u], q + u);
+    }
+    for (; q < q1; ++q) test(sxy[q], q);
+}
+
+// Candidates per loop iteration of the sweep (independent loads in flight).
+constexpr int kUnroll = 4;
+
+// NT threads per block, one agent (in the new cell order) per thread; the
+// per-thread sector minima take v * NT * 4 bytes of dynamic LDS.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, int v,
-                                              float *__restrict__ obs,
+__global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
+                                              int n_envs, int G, int v, float *__restrict__ obs,
                                               float *__restrict__ reward, int add_ret) {
     extern __shared__ uint32_t s_min[];  // [v][NT]
     __shared__ int s_env;
     const int p0 = blockIdx.x * NT;
     if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
     __syncthreads();
-    const int p = p0 + threadIdx.x;
-    if (p >= G) return;
+    const int tid = threadIdx.x;
+    const int pos = p0 + tid;
+    if (pos >= G) return;
     int e = s_env;
-    while (a.base[e + 1] <= p) ++e;
-    const DevEnv &E = a.envs[e];
-
-    uint32_t *smin = s_min + threadIdx.x;
+    while (a.base[e + 1] <= pos) ++e;
+    const DevEnv &E = envs[e];
+    const int j = pos - E.agent_base;
+    const float4 me = E.rec_nxt[j];
+    double sd, cd;
+    sincos((double)me.z, &sd, &cd);
+    const float c = (float)cd, s = (float)sd;
+    uint32_t *smin = s_min + tid;
     for (int k = 0; k < v; ++k) smin[k * NT] = kInfBits;
 
-    const float2 me = a.sxy[p];
-    const float2 cs = a.scs[p];
-    const float L = E.box;
+    const float vf = (float)v;
+    const float L = E.box, r2 = E.r2, c2 = E.c2;
     const int ncell = E.ncell, cb = E.cell_base;
-    const PairConst K{E.r2, E.c2, cs.x, cs.y, (float)v, v};
-    PairAcc acc{0, 0};
-
+    int nb = 0, col = 0;
     if (ncell == 1) {
-        const int q0 = a.start[cb], q1 = a.start[cb + 1];
-        for (int q = q0; q < q1; ++q) {
-            const float2 pj = a.sxy[q];
-            pair_test<NT>(min_image_delta(pj.x, me.x, L), min_image_delta(pj.y, me.y, L), q != p, K,
-                          smin, acc);
-        }
+        sweep_run<NT, kUnroll>(smin, a.sxy, a.start[cb], a.start[cb + 1], pos, 0.0f, me.x, 0.0f,
+                               me.y, true, L, r2, c2, c, s, vf, v, nb, col);
     } else {
         const int reach = E.reach;
         const int cx = cell_of(me.x, E.inv_cell, ncell);
@@ -430,49 +488,50 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, int n_envs, int G, i
             }
             const int colb = cb + ccx * ncell;
             if (lo < 0) {
-                sweep_run<NT>(a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell], p, offx, xi,
-                          -L, me.y, K, smin, acc);
-                sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi + 1], p, offx, xi, 0.0f, me.y,
-                          K, smin, acc);
+                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
+                                       pos, offx, xi, -L, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
+                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], pos, offx,
+                                       xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
             } else if (hi >= ncell) {
-                sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + ncell], p, offx, xi, 0.0f,
-                          me.y, K, smin, acc);
-                sweep_run<NT>(a.sxy, a.start[colb], a.start[colb + hi - ncell + 1], p, offx, xi, 0.0f,
-                          me.y - L, K, smin, acc);
+                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], pos,
+                                       offx, xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
+                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
+                                       pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, c, s, vf, v,
+                                       nb, col);
             } else {
-                sweep_run<NT>(a.sxy, a.start[colb + lo], a.start[colb + hi + 1], p, offx, xi, 0.0f,
-                          me.y, K, smin, acc);
+                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], pos,
+                                       offx, xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
             }
         }
     }
 
-    const int g = a.perm[p];
-    const int i = g - E.agent_base;
-    const float R = E.radius;
-    float *orow = obs ? obs + (size_t)g * v : E.obs + (size_t)i * v;
+    const int id = E.id_nxt[j];
+    const float inv_r = E.inv_radius;
+    float *orow = obs ? obs + ((size_t)E.agent_base + id) * v : E.obs + (size_t)id * v;
     if ((v & 3) == 0) {
         for (int k = 0; k < v; k += 4) {
             float o[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t m = smin[(k + j) * NT];
-                o[j] = m == kInfBits ? 0.0f : 1.0f - sqrtf(__uint_as_float(m)) / R;
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t m = smin[(k + u) * NT];
+                o[u] = m == kInfBits ? 0.0f
+                                     : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
             }
             *reinterpret_cast<float4 *>(orow + k) = make_float4(o[0], o[1], o[2], o[3]);
         }
     } else {
         for (int k = 0; k < v; ++k) {
             const uint32_t m = smin[k * NT];
-            orow[k] = m == kInfBits ? 0.0f : 1.0f - sqrtf(__uint_as_float(m)) / R;
+            orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
         }
     }
-    const float r = E.r_nb * (float)acc.nb + E.r_col * (float)acc.col;
-    if (reward) reward[g] = r;
-    else if (E.rew) E.rew[i] = r;
-    if (add_ret) E.ret[i] += (double)r;
+    const float r = E.r_nb * (float)nb + E.r_col * (float)col;
+    if (reward) reward[E.agent_base + id] = r;
+    else if (E.rew) E.rew[id] = r;
+    if (add_ret) E.ret_nxt[j] += (double)r;
     if (E.nb) {
-        E.nb[i] = acc.nb;
-        E.col[i] = acc.col;
+        E.nb[id] = nb;
+        E.col[id] = col;
     }
 }
 
@@ -484,14 +543,29 @@ __global__ void k_clear(int32_t *count, int64_t C, uint32_t *ticket) {
     if (i == 0) *ticket = 0u;
 }
 
-__global__ void k_copy_state(const float *sx, const float *sy, const float *sth, const float *ss,
-                             float *dx, float *dy, float *dth, float *ds, int n) {
+__global__ void k_load_state(const float *x, const float *y, const float *th, const float *sp,
+                             float4 *rec, int32_t *id, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    dx[i] = sx[i];
-    dy[i] = sy[i];
-    dth[i] = sth[i];
-    ds[i] = ss[i];
+    rec[i] = make_float4(x[i], y[i], th[i], sp[i]);
+    id[i] = i;
+}
+
+__global__ void k_store_state(const float4 *rec, const int32_t *id, float *x, float *y, float *th,
+                              float *sp, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float4 r = rec[p];
+    const int i = id[p];
+    x[i] = r.x;
+    y[i] = r.y;
+    th[i] = r.z;
+    sp[i] = r.w;
+}
+
+__global__ void k_store_returns(const double *ret, const int32_t *id, double *out, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) out[id[p]] = ret[p];
 }
 
 __global__ void k_zero_f64(double *p, int64_t n) {
@@ -500,11 +574,6 @@ __global__ void k_zero_f64(double *p, int64_t n) {
 }
 
 __global__ void k_copy_i32(const int32_t *src, int32_t *dst, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
-__global__ void k_copy_f64(const double *src, double *dst, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
@@ -521,13 +590,12 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
     a->sxy = cv.take<float2>(G);
-    a->scs = cv.take<float2>(G);
-    a->perm = cv.take<int32_t>(G);
     a->count = cv.take<int32_t>(C);
     a->start = cv.take<int32_t>(C + 1);
     a->part = cv.take<int32_t>(nb + 1);
     a->ticket = cv.take<uint32_t>(1);
-    a->envs = cv.take<DevEnv>(E);
+    a->envs[0] = cv.take<DevEnv>(E);
+    a->envs[1] = cv.take<DevEnv>(E);
     a->base = cv.take<int32_t>(E + 1);
 }
 
@@ -538,13 +606,14 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *obs,
+hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
                        float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
     if (p.G == 0) return hipSuccess;
     const int G = (int)p.G, C = (int)p.C;
+    const DevEnv *envs = p.a.envs[table & 1];
     const unsigned nb = blocks_for(G, kBlock);
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, p.n_envs, G, do_move,
+    hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G, do_move,
                        reinterpret_cast<const float2 *>(act));
     if (ev) (void)hipEventRecord(ev[1], s);
     if (p.scan_blocks == 0) {
@@ -556,26 +625,41 @@ hipError_t launch_step(const StepPlan &p, int do_move, const float *act, float *
                            p.a.part, p.a.start, C);
     }
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, G);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G);
     if (ev) (void)hipEventRecord(ev[3], s);
     if (p.v <= 32) {
         const size_t lds = (size_t)p.v * 256 * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<256>, dim3(blocks_for(G, 256)), dim3(256), lds, s, p.a,
+        hipLaunchKernelGGL(k_sweep<256>, dim3(blocks_for(G, 256)), dim3(256), lds, s, p.a, envs,
                            p.n_envs, G, p.v, obs, reward, add_return);
     } else {
         const size_t lds = (size_t)p.v * 64 * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<64>, dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a, p.n_envs,
-                           G, p.v, obs, reward, add_return);
+        hipLaunchKernelGGL(k_sweep<64>, dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a, envs,
+                           p.n_envs, G, p.v, obs, reward, add_return);
     }
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_state(const float *sx, const float *sy, const float *sth, const float *ss,
-                             float *dx, float *dy, float *dth, float *ds, int n, hipStream_t s) {
+hipError_t launch_load_state(const float *x, const float *y, const float *th, const float *sp,
+                             float4 *rec, int32_t *id, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_state, dim3(blocks_for(n, 256)), dim3(256), 0, s, sx, sy, sth, ss,
-                       dx, dy, dth, ds, n);
+    hipLaunchKernelGGL(k_load_state, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, th, sp, rec,
+                       id, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_state(const float4 *rec, const int32_t *id, float *x, float *y, float *th,
+                              float *sp, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_state, dim3(blocks_for(n, 256)), dim3(256), 0, s, rec, id, x, y, th,
+                       sp, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_returns(const double *ret, const int32_t *id, double *out, int n,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_returns, dim3(blocks_for(n, 256)), dim3(256), 0, s, ret, id, out, n);
     return hipGetLastError();
 }
 
@@ -588,12 +672,6 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

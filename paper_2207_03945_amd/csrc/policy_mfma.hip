@@ -210,15 +210,15 @@ hipError_t policy_launch(const pol_t *p, const float *obs, int64_t n, float *act
     return hipGetLastError();
 }
 
-hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, hipStream_t s) {
+hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, int table, hipStream_t s) {
     const int64_t n = plan.G;
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay, p->in_dim,
-                       p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr, plan.a.envs,
-                       plan.a.base, plan.n_envs);
+                       p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr,
+                       plan.a.envs[table & 1], plan.a.base, plan.n_envs);
     return hipGetLastError();
 }
 

@@ -103,8 +103,9 @@ struct flock_server {
     ArenaAlloc alloc;
     Block scratch;
     StepPlan plan{};
-    std::vector<DevEnv> descs;
+    std::vector<DevEnv> tab[2];   // [t]: each running env oriented for tick parity t
     std::vector<int32_t> base;
+    int table = 0;                // table of the next tick
     bool dirty = true;
     std::deque<int64_t> queue;
     std::map<int64_t, Request> reqs;
@@ -208,18 +209,20 @@ void admit_queued(srv_t *S) {
 }
 
 int rebuild_plan(srv_t *S) {
-    S->descs.clear();
+    for (auto &t : S->tab) t.clear();
     S->base.clear();
     int64_t g = 0, c = 0;
     for (int64_t id : S->running) {
         Request &r = S->reqs.at(id);
-        DevEnv d = env_descriptor(r.env);
-        d.agent_base = (int32_t)g;
-        d.cell_base = (int32_t)c;
-        d.act = r.act;
-        d.obs = r.obs;
-        d.rew = r.rew;
-        S->descs.push_back(d);
+        for (int f = 0; f < 2; ++f) {
+            DevEnv d = env_descriptor(r.env, f);
+            d.agent_base = (int32_t)g;
+            d.cell_base = (int32_t)c;
+            d.act = r.act;
+            d.obs = r.obs;
+            d.rew = r.rew;
+            S->tab[f].push_back(d);
+        }
         S->base.push_back((int32_t)g);
         g += r.p.n_agents;
         c += env_cell_count(r.env);
@@ -231,15 +234,17 @@ int rebuild_plan(srv_t *S) {
     S->plan.G = g;
     S->plan.C = c;
     S->plan.v = S->running.empty() ? 1 : S->reqs.at(S->running[0]).p.sectors;
-    S->plan.flags = 0;
     S->plan.scan_blocks = scan_blocks_for(c);
-    hipError_t e = hipMemcpyAsync(S->plan.a.envs, S->descs.data(), S->descs.size() * sizeof(DevEnv),
-                                  hipMemcpyHostToDevice, S->stream);
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 2 && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(S->plan.a.envs[f], S->tab[f].data(), S->tab[f].size() * sizeof(DevEnv),
+                           hipMemcpyHostToDevice, S->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->plan.a.base, S->base.data(), S->base.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, S->stream);
     if (e == hipSuccess) e = launch_clear(S->plan, S->stream);
     if (e != hipSuccess) return set_error(ENV_EHIP, "serving plan upload: %s", hipGetErrorString(e));
+    S->table = 0;
     S->dirty = false;
     return ENV_OK;
 }
@@ -330,10 +335,13 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
     int rc = ENV_OK;
     if (S->dirty) rc = rebuild_plan(S);
     if (rc != ENV_OK) return rc;
-    hipError_t e = policy_launch_envs(S->pol, S->plan, S->stream);
-    if (e == hipSuccess) e = launch_step(S->plan, 1, nullptr, nullptr, nullptr, 1, S->stream);
+    hipError_t e = policy_launch_envs(S->pol, S->plan, S->table, S->stream);
+    if (e == hipSuccess)
+        e = launch_step(S->plan, S->table, 1, nullptr, nullptr, nullptr, 1, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return set_error(ENV_EHIP, "srv_tick: %s", hipGetErrorString(e));
+    for (int64_t id : S->running) env_advance(S->reqs.at(id).env, 1);
+    S->table ^= 1;
     if (agents) *agents = S->plan.G;
     std::vector<int64_t> still;
     bool changed = false;
@@ -346,9 +354,17 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
         }
         r.ret.assign(r.p.n_agents, 0.0);
         if (r.p.n_agents > 0) {
-            const DevEnv d = env_descriptor(r.env);
-            e = hipMemcpy(r.ret.data(), d.ret, r.ret.size() * sizeof(double), hipMemcpyDeviceToHost);
+            // returns and agent ids of the current (cell-order) buffer
+            const DevEnv d = env_descriptor(r.env, 0);
+            std::vector<double> ret_cell(r.p.n_agents);
+            std::vector<int32_t> id_cell(r.p.n_agents);
+            e = hipMemcpy(ret_cell.data(), d.ret_cur, ret_cell.size() * sizeof(double),
+                          hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(id_cell.data(), d.id_cur, id_cell.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost);
             if (e != hipSuccess) return set_error(ENV_EHIP, "returns download: %s", hipGetErrorString(e));
+            for (size_t p = 0; p < id_cell.size(); ++p) r.ret[id_cell[p]] = ret_cell[p];
         }
         r.state = 2;
         release_request_blocks(S, r);

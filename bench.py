@@ -34,6 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+# FP32 vector issue: 256 CUs x 64 lanes x 2.4 GHz, one lane-op per lane per
+# clock (157.3 TFLOP/s counts an FMA as 2 and packed FP32 as 2 more; packed
+# FP32 is not generated here).
+VALU_PEAK = 256 * 64 * 2.4e9
+OPS_PER_CANDIDATE = 12     # image shift, d^2, radius and self tests, counts
+OPS_PER_NEIGHBOUR = 30     # bearing, sector, per-sector minimum
 V = 16                     # sectors of the paper-scale workloads
 STEP_BYTES = 44 + 4 * V    # algorithmic bytes per agent-step of the whole step
 SWEEP_BYTES = 8 + 4 + 4 * V + 4 + 16   # per agent: position, heading, view, reward, FP64 return r/w
@@ -47,15 +53,16 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def make_envs(flock, workloads, n, box, count, init, seed0):
+def make_envs(flock, workloads, n, box, count, init, seed0, **params):
     envs = []
     import torch
+    params = {"sectors": V, **params}
     for k in range(count):
         if init == "blobs":
             st = workloads.blob_state(n, box, seed=seed0 + k)
         else:
             st = workloads.uniform_state(n, box, seed=seed0 + k)
-        env = flock.Env(flock.Params(n_agents=n, box=box, sectors=V))
+        env = flock.Env(flock.Params(n_agents=n, box=box, **params))
         env.set_state(*[torch.from_numpy(a).cuda() for a in st])
         env.reset()
         envs.append(env)
@@ -77,7 +84,7 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20):
     import torch
     G = batch.n
     act = device_actions(G, K, seed)
-    obs = torch.empty(G, V, device="cuda")
+    obs = torch.empty(G, batch.d, device="cuda")
     rew = torch.empty(K, G, device="cuda")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -114,7 +121,7 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20):
 def bench_plain(env, n, K, W, seed):
     import torch
     act = device_actions(n, K, seed)
-    obs = torch.empty(n, V, device="cuda")
+    obs = torch.empty(n, env.d, device="cuda")
     rew = torch.empty(n, device="cuda")
     for t in range(W):
         env.step(act[t % K], obs, rew)
@@ -216,6 +223,47 @@ def cpu_baseline(seconds):
                       f"(move + all-pairs view/reward), {el:.1f} s"}
 
 
+def sweep_work(envs, radius=8.0):
+    """Candidate tests and neighbour pairs of one sweep over these envs' current states.
+
+    Candidates: for each agent, every agent of the (2 reach + 1)^2 cells round
+    its own (itself included; all n in a single-cell env).  Neighbours:
+    ordered pairs closer than the vision range (periodic k-d tree).
+    """
+    from scipy.spatial import cKDTree
+    cand = nbrs = 0
+    for e in envs:
+        x, y = (t.cpu().numpy().astype(np.float64) for t in e.get_state()[:2])
+        n = x.shape[0]
+        if n == 0:
+            continue
+        box = e.params.box
+        nc, reach, _ = e.geometry()
+        if nc == 1:
+            cand += n * n
+        else:
+            cx = np.minimum((x * (nc / box)).astype(np.int64), nc - 1)
+            cy = np.minimum((y * (nc / box)).astype(np.int64), nc - 1)
+            grid = np.zeros((nc, nc), np.int64)
+            np.add.at(grid, (cx, cy), 1)
+            block = np.zeros_like(grid)
+            for dx in range(-reach, reach + 1):
+                for dy in range(-reach, reach + 1):
+                    block += np.roll(np.roll(grid, dx, 0), dy, 1)
+            cand += int(block[cx, cy].sum())
+        pts = np.stack([np.mod(x, box), np.mod(y, box)], 1)
+        tree = cKDTree(pts, boxsize=box)
+        nbrs += int(tree.count_neighbors(tree, e.params.radius)) - n
+    return {"candidates": cand, "neighbours": nbrs,
+            "lane_ops": OPS_PER_CANDIDATE * cand + OPS_PER_NEIGHBOUR * nbrs}
+
+
+def alu_roofline(work, sweep_ms):
+    achieved = work["lane_ops"] / (sweep_ms * 1e-3)
+    return {"achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s",
+            "frac": achieved / VALU_PEAK}
+
+
 def sweep_source_hash():
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2207_03945_amd", "csrc", "flock_kernels.hip"), "rb") as f:
@@ -272,6 +320,7 @@ def main():
     main_res = bench_batched(flock, batch, K, W, seed=1)
     G = batch.n
     del batch
+    main_work = sweep_work(envs)
     extra = {}
     if not args.only_main:
         log("[bench] plain 5k")
@@ -305,6 +354,23 @@ def main():
                               "tuned_ms": {str(k): v for k, v in tune_ms.items()},
                               **bench_batched(flock, bu, K, W, seed=5, timed_reps=10)}
         del bu, envs_u
+        log("[bench] paper flock 10k")
+        pf = workloads.WORKLOADS["paper_flock10k"]
+        pf_params = dict(sectors=pf["sectors"], radius=pf["radius"],
+                         fov=math.radians(pf["fov_deg"]), flags=flock.ENV_FLAG_SPEED_OBS)
+        e10 = make_envs(flock, workloads, pf["n"], pf["box"], 20, "uniform", 3000, **pf_params)
+        plain = bench_plain(e10[0], pf["n"], K, W, seed=6)
+        b10 = flock.Batch(e10)
+        bat = bench_batched(flock, b10, K, W, seed=7, timed_reps=10)
+        work = sweep_work(e10)
+        pf_bytes = 8 + 4 + 4 * (pf["sectors"] + 1) + 4 + 16
+        extra["paper_flock10k"] = {
+            "workload": "20 envs x 10,000 agents, side 100, vision 10 (L/10), 128 sectors, "
+                        "field of view 250 degrees, speed appended (129 values)",
+            "plain": plain, "batched_x20": bat, "sweep_work_per_launch": work,
+            "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"]),
+            "sweep_hbm_frac": pf_bytes * b10.n / (bat["phase_ms"]["sweep"] * 1e-3) / HBM_PEAK}
+        del b10, e10
         log("[bench] serving")
         extra["serving"] = bench_serving(flock, workloads, args.serve_seconds)
     else:
@@ -319,13 +385,18 @@ def main():
         del src, dst
 
     sweep_ms = main_res["phase_ms"]["sweep"]
-    achieved = SWEEP_BYTES * G / (sweep_ms * 1e-3)
+    hbm_achieved = SWEEP_BYTES * G / (sweep_ms * 1e-3)
     traffic = traffic_from_profiles(G)
-    roofline = {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "algorithmic_bytes_per_launch": SWEEP_BYTES * G,
-                "avg_launch_ms": sweep_ms,
-                "step_frac": main_res["agent_steps_per_s"] * STEP_BYTES / HBM_PEAK}
+    # The sweep is bound by vector-ALU issue (tests and sector binning per
+    # candidate), not by its bytes: the ALU roofline is the binding one.
+    roofline = {"kernel": "k_sweep", "bound": "alu", **alu_roofline(main_work, sweep_ms),
+                "traffic": traffic, "avg_launch_ms": sweep_ms,
+                "work_per_launch": main_work,
+                "ops_model": f"{OPS_PER_CANDIDATE} lane-ops per candidate test + "
+                             f"{OPS_PER_NEIGHBOUR} per neighbour",
+                "hbm": {"algorithmic_bytes_per_launch": SWEEP_BYTES * G,
+                        "achieved_GBps": hbm_achieved / 1e9, "frac": hbm_achieved / HBM_PEAK},
+                "step_hbm_frac": main_res["agent_steps_per_s"] * STEP_BYTES / HBM_PEAK}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -36,7 +36,8 @@
  * State layout (structure of arrays, FP32, agent order): x[n], y[n] in
  * [0, box), heading th[n] in [0, 2pi), speed s[n] in [s_min, s_max].
  * Actions act[n][2]: column 0 = turn (rad), column 1 = speed change.
- * View obs[n][v] (agent-major): 1 - d_min/radius per sector, 0 when empty.
+ * View obs[n][d] (agent-major), d = v, or v + 1 with ENV_FLAG_SPEED_OBS:
+ * 1 - d_min/radius per sector, 0 when empty, then the agent's speed.
  * Reward reward[n] = r_nb * n_neighbours + r_col * n_collisions.
  */
 #ifndef FLOCKENV_H
@@ -64,7 +65,8 @@ enum {
 };
 
 /* flags */
-#define ENV_FLAG_COUNTS 1 /* keep per-agent neighbour / collision counts */
+#define ENV_FLAG_COUNTS 1    /* keep per-agent neighbour / collision counts   */
+#define ENV_FLAG_SPEED_OBS 2 /* append the agent's speed to its view row      */
 
 /*
  * Environment parameters (Sec. 4.1).  Requirements, else ENV_EINVAL:
@@ -75,6 +77,12 @@ enum {
  * cells are at least radius/cell_reach wide, so a (2 cell_reach + 1)^2 block
  * of cells covers the vision disc.  Boxes narrower than three cells use a
  * single cell and compare all pairs; the result does not depend on this.
+ * fov: field of view in radians, in [0, 2pi] (FP32 2pi); 0 and 2pi mean
+ * all round (Sec. 5 uses about 250 degrees).  With a full view sector 0 starts at the heading;
+ * with a limited view the v sectors split the arc [-fov/2, fov/2) round the
+ * heading from its right edge, counter-clockwise.  Agents outside the arc
+ * are not seen but still count in the reward (Eq. (1)).  A coincident
+ * agent is taken to lie on the heading.
  */
 typedef struct env_params {
     int32_t n_agents;
@@ -90,6 +98,7 @@ typedef struct env_params {
     float s_max;
     int32_t cell_reach;
     int32_t flags;     /* ENV_FLAG_*                                     */
+    float fov;         /* field of view (radians), 0 = full              */
 } env_params_t;
 
 typedef struct flock_env env_t;
@@ -128,12 +137,12 @@ int env_set_state(env_t *env, const float *x, const float *y, const float *th,
 int env_get_state(env_t *env, float *x, float *y, float *th, float *s, void *stream);
 
 /* Start an episode from the current state: zero the FP64 returns and compute
- * the initial view obs (device [n][v] FP32) without moving.  Requires a
+ * the initial view obs (device [n][d] FP32) without moving.  Requires a
  * prior env_set_state, else ENV_ESTATE. */
 int env_reset(env_t *env, float *obs, void *stream);
 
 /* One step (Sec. 4.1 order): apply act (device [n][2]) to every agent, move,
- * then write the view obs (device [n][v]) and reward (device [n]) of the new
+ * then write the view obs (device [n][d]) and reward (device [n]) of the new
  * positions, and add the reward to the FP64 returns.  ENV_ESTATE before
  * env_reset. */
 int env_step(env_t *env, const float *act, float *obs, float *reward, void *stream);
@@ -147,8 +156,9 @@ int env_get_returns(env_t *env, double *ret, void *stream);
 
 /* ---------------------------------------------------------------- batch */
 
-/* Several environments (possibly of different sizes and boxes, equal
- * `sectors`) stepped together by one sequence of launches.  Agents of env k
+/* Several environments (possibly of different sizes, boxes and views;
+ * equal `sectors` and ENV_FLAG_SPEED_OBS) stepped together by one sequence
+ * of launches.  Agents of env k
  * occupy rows [off[k], off[k+1]) of the batch-wide act/obs/reward arrays,
  * with off[k] = sum of n_agents of envs 0..k-1 (see env_batch_offsets).
  * Results are bitwise identical to stepping each env with env_step. */
@@ -166,12 +176,12 @@ void env_batch_destroy(env_batch_t *b);
 int env_batch_offsets(const env_batch_t *b, int64_t *off);
 
 /* One step of every env in the batch.  act: device [G][2], obs: device
- * [G][v], reward: device [G], G = off[n_envs]. */
+ * [G][d] (d as for env_step), reward: device [G], G = off[n_envs]. */
 int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward,
                      void *stream);
 
 /* k_steps consecutive batched steps replayed from a captured HIP graph.
- * act: device [k_steps][G][2] (step-major), obs: device [G][v] (final view),
+ * act: device [k_steps][G][2] (step-major), obs: device [G][d] (final view),
  * reward: device [k_steps][G].  The graph is captured on the first call and
  * re-captured when any argument changes. */
 int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs,
@@ -192,8 +202,10 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
 /* --------------------------------------------------------------- policy */
 
 /* Shared policy network of Sec. 4.3/5: in -> hidden -> hidden -> 2, tanh on
- * every layer, output scaled by (max_turn, max_dspeed).  in must equal the
- * envs' sector count and lie in [1, 32]; hidden = 64. */
+ * every layer, output scaled by (max_turn, max_dspeed).  in lies in
+ * [1, 257] and, where the policy drives envs, equals their view row length
+ * d (sectors, + 1 with ENV_FLAG_SPEED_OBS); hidden = 64.  Sec. 5's flock
+ * network reads d = 129 (128 sectors and the speed). */
 size_t pol_workspace_bytes(int in_dim, int hidden);
 
 /* w_host: FP32 host array W1[in][hidden], b1[hidden], W2[hidden][hidden],
@@ -208,7 +220,7 @@ void pol_destroy(pol_t *pol);
 int pol_forward(pol_t *pol, const float *obs, int64_t n, float *act, void *stream);
 
 /* Closed-loop batched step: act = policy(obs) for every agent, then one
- * batched step with those actions.  obs (device [G][v]) is read as the
+ * batched step with those actions.  obs (device [G][d]) is read as the
  * current view and overwritten by the new one; act (device [G][2]) receives
  * the actions taken; reward (device [G]). */
 int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
@@ -219,7 +231,9 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
 /* Continuous-batching server.  `arena` (device, `arena_bytes`) is the HBM
  * budget: each admitted request's env workspace, view/action/reward rows and
  * the tick's batch scratch are carved from it.  At most max_slots requests
- * run at once.  All requests share `pol` and must have sectors == pol's in.
+ * run at once.  All requests share `pol`: their view row length d must
+ * equal pol's in, and every request has the sector count of the first one
+ * submitted (ENV_EINVAL otherwise).  Fields of view may differ.
  */
 int srv_create(void *arena, size_t arena_bytes, int max_slots, pol_t *pol,
                void *stream, srv_t **out);

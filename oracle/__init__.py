@@ -14,6 +14,7 @@ against closed forms, brute-force lattice counts, invariants and statistics.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -53,7 +54,7 @@ def _load():
         opt_i32 = ctypes.c_void_p
         lib.oracle_sense.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                     ctypes.c_double, _f32p, _f32p, _f32p,
+                                     ctypes.c_double, ctypes.c_double, _f32p, _f32p, _f32p,
                                      ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_double,
                                      _f64p, _i32p, _i32p, _f64p,
@@ -91,13 +92,17 @@ class SenseResult:
         self.__dict__.update(kw)
 
 
+TWO_PI = 2.0 * math.pi
+
+
 def oracle_sense(x, y, th, box, radius=8.0, collide=0.5, sectors=16, r_nb=0.1, r_col=-1.0,
-                 agents=None, eps_d=0.0, eps_phi=0.0) -> SenseResult:
+                 agents=None, eps_d=0.0, eps_phi=0.0, fov=TWO_PI) -> SenseResult:
     """View + reward for the agents in ``agents`` (all if None), all-pairs, FP64.
 
     Follows Sec. 4 (v sectors, nearest distance per sector), Sec. 4.1 Eq. (1)
     (sum over d_ij < d_v) and Fig. 4's collision penalty.  ``eps_d``/``eps_phi``
-    request the ambiguity bands described in ``flock_oracle.c``.
+    request the ambiguity bands described in ``flock_oracle.c``; ``fov`` < 2 pi
+    restricts the view to that arc round the heading (Sec. 5).
     """
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
@@ -122,7 +127,7 @@ def oracle_sense(x, y, th, box, radius=8.0, collide=0.5, sectors=16, r_nb=0.1, r
     dloose = np.zeros((n_list, sectors), np.float64)
     if n_list > 0:
         _load().oracle_sense(n, float(box), float(radius), float(collide), int(sectors),
-                             float(r_nb), float(r_col), x, y, th, n_list, lst_ptr,
+                             float(fov), float(r_nb), float(r_col), x, y, th, n_list, lst_ptr,
                              float(eps_d), float(eps_phi), obs, n_nb, n_col, reward,
                              nb_lo.ctypes.data, nb_hi.ctypes.data, col_lo.ctypes.data,
                              col_hi.ctypes.data, dstrict.ctypes.data, dloose.ctypes.data)
@@ -131,11 +136,24 @@ def oracle_sense(x, y, th, box, radius=8.0, collide=0.5, sectors=16, r_nb=0.1, r
                        dmin_loose=dloose, agents=lst)
 
 
+def observation(sense, speed=None):
+    """The agent's observation: its v-sector view, then its speed when given.
+
+    Sec. 4.1 describes the flock observation as the view followed by the
+    agent's current speed (129 = 128 sectors + speed).
+    """
+    if speed is None:
+        return sense.obs
+    rows = slice(None) if sense.agents is None else sense.agents
+    return np.concatenate([sense.obs, np.asarray(speed, np.float64)[rows, None]], axis=1)
+
+
 def oracle_step(state, act, box, radius=8.0, collide=0.5, sectors=16, r_nb=0.1, r_col=-1.0,
                 max_turn=0.2, max_dspeed=0.1, s_min=0.0, s_max=2.0, eps_d=0.0, eps_phi=0.0,
-                agents=None):
+                agents=None, fov=TWO_PI):
     """One full step (Sec. 4.1 order): move every agent, then sense."""
     new_state = oracle_move(state, act, box, max_turn, max_dspeed, s_min, s_max)
     sense = oracle_sense(new_state[0], new_state[1], new_state[2], box, radius, collide,
-                         sectors, r_nb, r_col, agents=agents, eps_d=eps_d, eps_phi=eps_phi)
+                         sectors, r_nb, r_col, agents=agents, eps_d=eps_d, eps_phi=eps_phi,
+                         fov=fov)
     return new_state, sense

@@ -40,8 +40,15 @@
  *          a neighbour.  Bearing phi = (atan2(dy, dx) - th_i) mod 2pi; sector
  *          k = min(v-1, floor(phi v / 2pi)); sector 0 starts at the heading and
  *          sectors advance counter-clockwise; a coincident pair (d = 0) is put
- *          in sector 0.  obs[i][k] = 1 - d_min(k)/R, or 0 if the sector is
- *          empty.  reward = r_nb * n_nb + r_col * n_col.
+ *          in sector 0 (it is taken to lie on the heading).  obs[i][k] =
+ *          1 - d_min(k)/R, or 0 if the sector is empty.
+ *          reward = r_nb * n_nb + r_col * n_col.
+ *   field of view (Sec. 5 gives the benchmark agents a convex field of view
+ *          of about 250 degrees): with fov < 2pi the v sectors split the arc
+ *          [-fov/2, fov/2) of bearings relative to the heading (wrapped into
+ *          (-pi, pi]), counter-clockwise from its right edge; a neighbour
+ *          outside the arc is not seen but still counts in the reward, since
+ *          Eq. (1) sums over every agent within the vision range.
  *
  * Tolerance bands.  With eps_d > 0 and eps_phi > 0 the oracle additionally
  * reports, per agent, the lowest and highest neighbour / collision counts and
@@ -56,6 +63,7 @@
 #include <stdint.h>
 
 #define TWO_PI_D 6.283185307179586476925286766559
+#define PI_D 3.1415926535897932384626433832795
 
 /* ------------------------------------------------------------------------ */
 /* Step part 1: rotate, accelerate, move (Sec. 4.1).                          */
@@ -132,6 +140,16 @@ static int sector_of(double phi, int v)
     return k;
 }
 
+/* Position of bearing phi (in [0, 2pi) from the heading) in sector units:
+ * [0, v) when visible.  Full view: phi v / 2pi.  Limited view: the bearing
+ * wrapped into (-pi, pi], shifted by fov/2, times v / fov. */
+static double view_position(double phi, int v, double fov)
+{
+    if (fov >= TWO_PI_D) return phi * (double)v / TWO_PI_D;
+    double rel = phi > PI_D ? phi - TWO_PI_D : phi;
+    return (rel + 0.5 * fov) * (double)v / fov;
+}
+
 /*
  * Sense every agent in `list` (or agents 0..n_list-1 when list is NULL)
  * against all n agents.
@@ -149,7 +167,7 @@ static int sector_of(double phi, int v)
  *   dmin_loose[n_list][v]   min distance over pairs possibly inside R and
  *                           possibly in the sector (INFINITY if none)
  */
-void oracle_sense(int n, double box, double radius, double collide, int v,
+void oracle_sense(int n, double box, double radius, double collide, int v, double fov,
                   double r_nb, double r_col,
                   const float *x, const float *y, const float *th,
                   int n_list, const int *list,
@@ -158,7 +176,8 @@ void oracle_sense(int n, double box, double radius, double collide, int v,
                   int *nb_lo, int *nb_hi, int *col_lo, int *col_hi,
                   double *dmin_strict, double *dmin_loose)
 {
-    const double eps_sector = eps_phi * (double)v / TWO_PI_D;
+    const int full = fov >= TWO_PI_D;
+    const double eps_sector = eps_phi * (double)v / (full ? TWO_PI_D : fov);
     if (v < 1 || v > 256) return;
 
 #pragma omp parallel for schedule(dynamic, 16)
@@ -182,15 +201,24 @@ void oracle_sense(int n, double box, double radius, double collide, int v,
             if (d >= radius + eps_d) continue;
 
             /* plain definition */
-            int k = 0;
-            double phi = 0.0;
+            int k = 0, seen = 1;
+            double t = 0.0;
             if (d > 0.0) {
-                phi = relative_bearing(dx, dy, thi);
-                k = sector_of(phi, v);
+                double phi = relative_bearing(dx, dy, thi);
+                t = view_position(phi, v, fov);
+                if (full) {
+                    k = sector_of(phi, v);
+                } else {
+                    seen = t >= 0.0 && t < (double)v;
+                    k = seen ? (int)floor(t) : -1;
+                }
+            } else if (!full) {
+                t = 0.5 * (double)v; /* coincident: straight ahead */
+                k = (int)floor(t);
             }
             if (d < radius) {
                 nb += 1;
-                if (d < dmin[k]) dmin[k] = d;
+                if (seen && d < dmin[k]) dmin[k] = d;
             }
             if (d < collide) col += 1;
 
@@ -203,13 +231,14 @@ void oracle_sense(int n, double box, double radius, double collide, int v,
 
             int k_lo = k, k_hi = k;
             if (d > 0.0 && eps_sector > 0.0) {
-                /* position in sector units; k_lo = -1 or k_hi = v wrap round */
-                double t = phi * (double)v / TWO_PI_D;
+                /* position in sector units; for a full view k_lo = -1 or
+                 * k_hi = v wrap round, for a limited view they fall outside */
                 k_lo = (int)floor(t - eps_sector);
                 k_hi = (int)floor(t + eps_sector);
             }
-            if (sure_in && k_lo == k_hi && d < dstrict[k]) dstrict[k] = d;
+            if (sure_in && seen && k_lo == k_hi && d < dstrict[k]) dstrict[k] = d;
             for (int kk = k_lo; kk <= k_hi; ++kk) {
+                if (!full && (kk < 0 || kk >= v)) continue;
                 int kw = ((kk % v) + v) % v;
                 if (d < dloose[kw]) dloose[kw] = d;
             }

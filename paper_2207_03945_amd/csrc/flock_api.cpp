@@ -63,9 +63,13 @@ int check_params(const env_params_t *p) {
     if (!finite(p->s_min) || !finite(p->s_max) || p->s_min < 0.0f || p->s_min > p->s_max)
         return fail(ENV_EINVAL, "need 0 <= s_min <= s_max");
     if (p->cell_reach < 0 || p->cell_reach > 2) return fail(ENV_EINVAL, "cell_reach must be 0, 1 or 2");
-    if (p->flags & ~ENV_FLAG_COUNTS) return fail(ENV_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(ENV_FLAG_COUNTS | ENV_FLAG_SPEED_OBS))
+        return fail(ENV_EINVAL, "unknown flags 0x%x", p->flags);
+    if (!finite(p->fov) || p->fov < 0.0f || p->fov > kTwoPiF)
+        return fail(ENV_EINVAL, "fov must be 0 (full view) or in (0, 2 pi]");
     return ENV_OK;
 }
+
 
 struct Geometry {
     int ncell, reach;
@@ -116,6 +120,16 @@ DevEnv make_desc(const env_params_t &p, const Geometry &gm) {
     d.max_dspeed = p.max_dspeed;
     d.s_min = p.s_min;
     d.s_max = p.s_max;
+    if (full_view(p)) {
+        d.fov_half = 0.0f;
+        d.fov_t = 1.0f;
+        d.sec_scale = (float)p.sectors;
+    } else {
+        const double t = (double)p.fov / (2.0 * M_PI);  // arc in turns
+        d.fov_t = (float)t;
+        d.fov_half = 0.5f * d.fov_t;
+        d.sec_scale = (float)((double)p.sectors / (double)d.fov_t);
+    }
     return d;
 }
 
@@ -150,6 +164,11 @@ EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
+
+bool flock::full_view(const env_params_t &p) { return p.fov == 0.0f || p.fov >= kTwoPiF; }
+int flock::obs_dim_of(const env_params_t &p) {
+    return p.sectors + ((p.flags & ENV_FLAG_SPEED_OBS) ? 1 : 0);
+}
 
 int flock::set_error(int code, const char *fmt, ...) {
     va_list ap;
@@ -313,6 +332,8 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.G = p->n_agents;
     e->plan.C = (int64_t)gm.ncell * gm.ncell;
     e->plan.v = p->sectors;
+    e->plan.obs_dim = obs_dim_of(*p);
+    e->plan.fov = full_view(*p) ? 0 : 1;
     e->plan.scan_blocks = scan_blocks_for(e->plan.C);
     *out = e;
     g_err.clear();
@@ -405,7 +426,8 @@ int env_get_returns(env_t *env, double *ret, void *stream) {
 // ------------------------------------------------------------------- batch
 
 static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *base,
-                        std::vector<int64_t> *off, int64_t *G, int64_t *C, int *v) {
+                        std::vector<int64_t> *off, int64_t *G, int64_t *C, int *v,
+                        int *obs_dim = nullptr, int *fov = nullptr) {
     if (!envs || n_envs < 1) return fail(ENV_EINVAL, "need at least one env");
     int64_t g = 0, c = 0;
     for (int k = 0; k < n_envs; ++k) {
@@ -414,6 +436,9 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *ba
         if (e->p.sectors != envs[0]->p.sectors)
             return fail(ENV_EINVAL, "env %d has %d sectors, env 0 has %d", k, e->p.sectors,
                         envs[0]->p.sectors);
+        if (obs_dim_of(e->p) != obs_dim_of(envs[0]->p))
+            return fail(ENV_EINVAL, "env %d and env 0 differ in ENV_FLAG_SPEED_OBS", k);
+        if (fov && !full_view(e->p)) *fov = 1;
         if (base) base->push_back((int32_t)g);
         if (off) off->push_back(g);
         g += e->p.n_agents;
@@ -426,6 +451,7 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *ba
     *G = g;
     *C = c;
     *v = envs[0]->p.sectors;
+    if (obs_dim) *obs_dim = obs_dim_of(envs[0]->p);
     return ENV_OK;
 }
 
@@ -443,8 +469,8 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
         return fail(ENV_EINVAL, "workspace must be 256-byte aligned");
     env_batch_t *b = new env_batch_t;
     int64_t G, C;
-    int v;
-    int rc = batch_layout(envs, n_envs, &b->base, &b->off, &G, &C, &v);
+    int v, obs_dim = 0, fov = 0;
+    int rc = batch_layout(envs, n_envs, &b->base, &b->off, &G, &C, &v, &obs_dim, &fov);
     if (rc != ENV_OK) {
         delete b;
         return rc;
@@ -468,6 +494,8 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.G = G;
     b->plan.C = C;
     b->plan.v = v;
+    b->plan.obs_dim = obs_dim;
+    b->plan.fov = fov;
     b->plan.scan_blocks = scan_blocks_for(C);
     *out = b;
     return ENV_OK;
@@ -650,8 +678,9 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
                     void *stream) {
     if (!b || !pol) return fail(ENV_EINVAL, "batch or policy is NULL");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
-    if (policy_in_dim(pol) != b->plan.v)
-        return fail(ENV_EINVAL, "policy input %d != sectors %d", policy_in_dim(pol), b->plan.v);
+    if (policy_in_dim(pol) != b->plan.obs_dim)
+        return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(pol),
+                    b->plan.obs_dim);
     hipStream_t s = as_stream(stream);
     int t;
     int rc = batch_prepare(b, s, &t);

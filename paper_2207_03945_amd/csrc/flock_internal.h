@@ -44,6 +44,10 @@ struct DevEnv {
     float inv_radius;            // 1 / radius (FP32)
     float r_nb, r_col;
     float max_turn, max_dspeed, s_min, s_max;
+    // View geometry in turns of the bearing from the heading: the arc
+    // position is (bearing + fov_half) mod 1, seen iff < fov_t, sector =
+    // position * sec_scale.  Full view: fov_half 0, fov_t 1, sec_scale v.
+    float fov_half, fov_t, sec_scale;
 };
 static_assert(sizeof(DevEnv) <= 192, "DevEnv grew");
 
@@ -68,6 +72,8 @@ struct StepPlan {
     int64_t G;    // agents
     int64_t C;    // cells
     int v;        // sectors
+    int obs_dim;  // view row length: v, or v + 1 with the speed appended
+    int fov;      // any env of the plan has a limited view
     int scan_blocks;  // 0 -> single-block scan
 };
 
@@ -117,6 +123,8 @@ hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStrea
 
 // Env internals used by the batch and serving layers (flock_api.cpp) -------
 int validate_params(const env_params_t *p);     // ENV_OK or ENV_EINVAL (+ message)
+bool full_view(const env_params_t &p);          // fov 0 or 2 pi: the whole circle
+int obs_dim_of(const env_params_t &p);          // view row length: sectors (+ 1 for speed)
 // Descriptor with agent_base = cell_base = 0, oriented so that rec_cur is
 // the env's current buffer (flip = 1 swaps cur and nxt).
 DevEnv env_descriptor(const env_t *env, int flip);

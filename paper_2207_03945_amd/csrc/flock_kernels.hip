@@ -389,6 +389,28 @@ __device__ __forceinline__ int sector_of(float dx, float dy, float c, float s, f
     return k < v - 1 ? k : v - 1;
 }
 
+// View sector of the bearing of (dx, dy) for a limited field of view: the
+// bearing in turns from the heading (as in sector_of), shifted by half the
+// arc and wrapped, is seen iff it lies in the arc; -1 when not seen.  A
+// coincident agent counts as straight ahead: the middle sector v/2.
+__device__ __forceinline__ int view_sector(float dx, float dy, float c, float s, float fov_half,
+                                           float fov_t, float sec_scale, int v) {
+    const float u = __builtin_fmaf(dx, c, dy * s);
+    const float w = __builtin_fmaf(dy, c, -(dx * s));
+    const float au = fabsf(u), aw = fabsf(w);
+    const float mx = fmaxf(au, aw), mn = fminf(au, aw);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    float a = atan_turns01(t);
+    a = aw > au ? 0.25f - a : a;
+    a = u < 0.0f ? 0.5f - a : a;
+    a = w < 0.0f ? 1.0f - a : a;
+    float p = a + fov_half;
+    p = p >= 1.0f ? p - 1.0f : p;
+    int k = (int)(p * sec_scale);
+    k = p < fov_t ? (k < v - 1 ? k : v - 1) : -1;
+    return mx > 0.0f ? k : (v >> 1);
+}
+
 // Periodic displacement for single-cell (all-pairs) envs: the shift by L is
 // applied to whichever operand lies in the far half, where it is exact.
 __device__ __forceinline__ float min_image_delta(float xj, float xi, float L) {
@@ -398,18 +420,27 @@ __device__ __forceinline__ float min_image_delta(float xj, float xi, float L) {
     return d;
 }
 
+// View constants of the lane's agent (see DevEnv).
+struct ViewK {
+    float c, s;                       // cos / sin of the heading
+    float fov_half, fov_t, sec_scale;
+    float vf;
+    int v;
+};
+
 // Test candidates [q, q1) against the lane's agent: distance test, and for a
 // neighbour the count, the collision count and the per-sector minimum (an
 // LDS atomic min on the lane's own slot).  The sector is computed for every
 // candidate (branch-free); only the LDS update is predicated.  (offx, xi),
 // (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis;
 // minimg selects the per-candidate minimum image (single-cell envs).
-template <int NT, int UNROLL>
+// kFov selects the limited-view sector (candidates outside the arc are
+// counted but update no sector).
+template <int NT, int UNROLL, bool kFov>
 __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
                                           int q, int q1, int self, float offx, float xi,
                                           float offy, float yi, bool minimg, float L, float r2,
-                                          float c2, float c, float s, float vf, int v, int &nb,
-                                          int &col) {
+                                          float c2, const ViewK &K, int &nb, int &col) {
     auto test = [&](const float2 pj, int qq) {
         float dx, dy;
         if (minimg) {
@@ -423,8 +454,13 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
         const bool nbr = d2 < r2 && qq != self;
         nb += nbr ? 1 : 0;
         col += (nbr && d2 < c2) ? 1 : 0;
-        const int k = sector_of(dx, dy, c, s, vf, v);
-        if (nbr) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+        if (kFov) {
+            const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
+            if (nbr && k >= 0) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+        } else {
+            const int k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
+            if (nbr) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+        }
     };
     for (; q + UNROLL <= q1; q += UNROLL) {
         float2 pj[UNROLL];
@@ -441,10 +477,13 @@ constexpr int kUnroll = 4;
 
 // NT threads per block, one agent (in the new cell order) per thread; the
 // per-thread sector minima take v * NT * 4 bytes of dynamic LDS.
-template <int NT>
+// kFov: some env of the launch has a limited field of view.  obs rows hold
+// obs_dim floats: the v sectors, then the speed when obs_dim > v.
+template <int NT, bool kFov>
 __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
-                                              int n_envs, int G, int v, float *__restrict__ obs,
-                                              float *__restrict__ reward, int add_ret) {
+                                              int n_envs, int G, int v, int obs_dim,
+                                              float *__restrict__ obs, float *__restrict__ reward,
+                                              int add_ret) {
     extern __shared__ uint32_t s_min[];  // [v][NT]
     __shared__ int s_env;
     const int p0 = blockIdx.x * NT;
@@ -464,13 +503,13 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     uint32_t *smin = s_min + tid;
     for (int k = 0; k < v; ++k) smin[k * NT] = kInfBits;
 
-    const float vf = (float)v;
+    const ViewK K{c, s, E.fov_half, E.fov_t, E.sec_scale, (float)v, v};
     const float L = E.box, r2 = E.r2, c2 = E.c2;
     const int ncell = E.ncell, cb = E.cell_base;
     int nb = 0, col = 0;
     if (ncell == 1) {
-        sweep_run<NT, kUnroll>(smin, a.sxy, a.start[cb], a.start[cb + 1], pos, 0.0f, me.x, 0.0f,
-                               me.y, true, L, r2, c2, c, s, vf, v, nb, col);
+        sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[cb], a.start[cb + 1], pos, 0.0f, me.x, 0.0f,
+                               me.y, true, L, r2, c2, K, nb, col);
     } else {
         const int reach = E.reach;
         const int cx = cell_of(me.x, E.inv_cell, ncell);
@@ -488,27 +527,27 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
             }
             const int colb = cb + ccx * ncell;
             if (lo < 0) {
-                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
-                                       pos, offx, xi, -L, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
-                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], pos, offx,
-                                       xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
+                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
+                                       pos, offx, xi, -L, me.y, false, L, r2, c2, K, nb, col);
+                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], pos, offx,
+                                       xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
             } else if (hi >= ncell) {
-                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], pos,
-                                       offx, xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
-                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
-                                       pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, c, s, vf, v,
-                                       nb, col);
+                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], pos,
+                                       offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
+                                       pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, K, nb, col);
             } else {
-                sweep_run<NT, kUnroll>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], pos,
-                                       offx, xi, 0.0f, me.y, false, L, r2, c2, c, s, vf, v, nb, col);
+                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], pos,
+                                       offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
             }
         }
     }
 
     const int id = E.id_nxt[j];
     const float inv_r = E.inv_radius;
-    float *orow = obs ? obs + ((size_t)E.agent_base + id) * v : E.obs + (size_t)id * v;
-    if ((v & 3) == 0) {
+    float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
+    if (obs_dim > v) orow[v] = me.w;  // speed after the move (Sec. 4.1)
+    if ((obs_dim & 3) == 0 && (v & 3) == 0) {
         for (int k = 0; k < v; k += 4) {
             float o[4];
 #pragma unroll
@@ -629,12 +668,20 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
     if (ev) (void)hipEventRecord(ev[3], s);
     if (p.v <= 32) {
         const size_t lds = (size_t)p.v * 256 * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<256>, dim3(blocks_for(G, 256)), dim3(256), lds, s, p.a, envs,
-                           p.n_envs, G, p.v, obs, reward, add_return);
+        if (p.fov)
+            hipLaunchKernelGGL((k_sweep<256, true>), dim3(blocks_for(G, 256)), dim3(256), lds, s,
+                               p.a, envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
+        else
+            hipLaunchKernelGGL((k_sweep<256, false>), dim3(blocks_for(G, 256)), dim3(256), lds, s,
+                               p.a, envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
     } else {
         const size_t lds = (size_t)p.v * 64 * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_sweep<64>, dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a, envs,
-                           p.n_envs, G, p.v, obs, reward, add_return);
+        if (p.fov)
+            hipLaunchKernelGGL((k_sweep<64, true>), dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a,
+                               envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
+        else
+            hipLaunchKernelGGL((k_sweep<64, false>), dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a,
+                               envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
     }
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();

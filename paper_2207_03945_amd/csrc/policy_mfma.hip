@@ -34,6 +34,8 @@ namespace {
 
 constexpr int kHidden = 64;
 constexpr int kPolBlock = 256;
+constexpr int kMaxIn = 257;                    // 256 sectors + speed
+constexpr int kRegChunks = 2;                  // layer-1 K chunks kept in registers
 
 // Device workspace of one policy.
 struct PolLayout {
@@ -81,6 +83,9 @@ __device__ __forceinline__ int env_of_row(const int32_t *base, int n_envs, int64
 
 // Rows are agents; obs/act are [n][in_dim] / [n][2] arrays, or, when `envs`
 // is non-null, each row's env-owned rows found through the batch tables.
+// kLdsW1: the layer-1 A operand (kc1 > kRegChunks chunks of 16 inputs) is
+// staged in dynamic LDS once per block instead of living in registers.
+template <bool kLdsW1>
 __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
                                                       float max_turn, float max_dspeed,
                                                       const float *__restrict__ obs, int64_t n,
@@ -88,6 +93,9 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                                                       const DevEnv *__restrict__ envs,
                                                       const int32_t *__restrict__ base, int n_envs) {
     __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
+    extern __shared__ bf16x8 s_w1[];  // [kc1][2 tiles][64 lanes] when kLdsW1
+    if (kLdsW1)
+        for (int i = threadIdx.x; i < kc1 * 128; i += kPolBlock) s_w1[i] = P.w1f[i];
     for (int i = threadIdx.x; i < 64; i += kPolBlock) {
         s_b1[i] = P.b1l[i];
         s_b2[i] = P.b2l[i];
@@ -97,10 +105,11 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
     __syncthreads();
 
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
-    bf16x8 w1[2][2];
-    for (int kc = 0; kc < 2; ++kc)
-        for (int t = 0; t < 2; ++t)
-            w1[kc][t] = kc < kc1 ? P.w1f[(kc * 2 + t) * 64 + lane] : bf16x8{};
+    bf16x8 w1[kRegChunks][2];
+    if (!kLdsW1)
+        for (int kc = 0; kc < kRegChunks; ++kc)
+            for (int t = 0; t < 2; ++t)
+                w1[kc][t] = kc < kc1 ? P.w1f[(kc * 2 + t) * 64 + lane] : bf16x8{};
     bf16x8 w2[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
         for (int kc = 0; kc < kc1; ++kc) {
             bf16x8 xb;
             const int k0 = 16 * kc + 8 * g;
-            if (valid && in_dim % 8 == 0 && k0 + 8 <= in_dim) {
+            if (valid && in_dim % 4 == 0 && k0 + 8 <= in_dim) {
                 const float4 *src = reinterpret_cast<const float4 *>(orow + k0);
                 const float4 u = src[0], w = src[1];
                 xb[0] = (__bf16)u.x; xb[1] = (__bf16)u.y; xb[2] = (__bf16)u.z; xb[3] = (__bf16)u.w;
@@ -137,8 +146,16 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                     xb[j] = (__bf16)((valid && k < in_dim) ? orow[k] : 0.0f);
                 }
             }
-            acc1[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[kc][0], xb, acc1[0], 0, 0, 0);
-            acc1[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[kc][1], xb, acc1[1], 0, 0, 0);
+            bf16x8 a0, a1;
+            if constexpr (kLdsW1) {
+                a0 = s_w1[(kc * 2 + 0) * 64 + lane];
+                a1 = s_w1[(kc * 2 + 1) * 64 + lane];
+            } else {
+                a0 = w1[kc][0];
+                a1 = w1[kc][1];
+            }
+            acc1[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, xb, acc1[0], 0, 0, 0);
+            acc1[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, xb, acc1[1], 0, 0, 0);
         }
         // bias + tanh; registers 8 (c % 2) .. + 8 of tile c / 2 are chunk c of layer 2's K
         bf16x8 h1[4];
@@ -199,14 +216,24 @@ struct flock_policy {
 
 namespace flock {
 
+namespace {
+size_t w1_lds_bytes(int kc1) { return (size_t)kc1 * 2 * 64 * sizeof(bf16x8); }
+}  // namespace
+
 hipError_t policy_launch(const pol_t *p, const float *obs, int64_t n, float *act, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay, p->in_dim,
-                       p->kc1, p->max_turn, p->max_dspeed, obs, n, reinterpret_cast<float2 *>(act),
-                       nullptr, nullptr, 0);
+    if (p->kc1 > kRegChunks)
+        hipLaunchKernelGGL(k_policy<true>, dim3((unsigned)blocks), dim3(kPolBlock),
+                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
+                           p->max_dspeed, obs, n, reinterpret_cast<float2 *>(act), nullptr, nullptr,
+                           0);
+    else
+        hipLaunchKernelGGL(k_policy<false>, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay,
+                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n,
+                           reinterpret_cast<float2 *>(act), nullptr, nullptr, 0);
     return hipGetLastError();
 }
 
@@ -216,9 +243,15 @@ hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, int table, h
     const int64_t tiles = (n + 31) / 32;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_policy, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay, p->in_dim,
-                       p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr,
-                       plan.a.envs[table & 1], plan.a.base, plan.n_envs);
+    if (p->kc1 > kRegChunks)
+        hipLaunchKernelGGL(k_policy<true>, dim3((unsigned)blocks), dim3(kPolBlock),
+                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
+                           p->max_dspeed, nullptr, n, nullptr, plan.a.envs[table & 1], plan.a.base,
+                           plan.n_envs);
+    else
+        hipLaunchKernelGGL(k_policy<false>, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay,
+                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr,
+                           plan.a.envs[table & 1], plan.a.base, plan.n_envs);
     return hipGetLastError();
 }
 
@@ -229,8 +262,8 @@ int policy_in_dim(const pol_t *p) { return p->in_dim; }
 extern "C" {
 
 size_t pol_workspace_bytes(int in_dim, int hidden) {
-    if (in_dim < 1 || in_dim > 32 || hidden != kHidden) {
-        set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= 32 and hidden == 64");
+    if (in_dim < 1 || in_dim > kMaxIn || hidden != kHidden) {
+        set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= %d and hidden == 64", kMaxIn);
         return 0;
     }
     return carve_pol(nullptr, (in_dim + 15) / 16).bytes;
@@ -239,8 +272,8 @@ size_t pol_workspace_bytes(int in_dim, int hidden) {
 int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max_dspeed, void *ws,
                size_t bytes, void *stream, pol_t **out) {
     if (!w || !ws || !out) return set_error(ENV_EINVAL, "NULL argument to pol_create");
-    if (in_dim < 1 || in_dim > 32 || hidden != kHidden)
-        return set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= 32 and hidden == 64");
+    if (in_dim < 1 || in_dim > kMaxIn || hidden != kHidden)
+        return set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= %d and hidden == 64", kMaxIn);
     if (!(max_turn >= 0.0f) || !(max_dspeed >= 0.0f) || !isfinite(max_turn) || !isfinite(max_dspeed))
         return set_error(ENV_EINVAL, "action scales must be finite and >= 0");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)

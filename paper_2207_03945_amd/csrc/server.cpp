@@ -88,7 +88,7 @@ struct Request {
 
 size_t io_bytes(const env_params_t &p) {
     const size_t n = (size_t)p.n_agents;
-    return align_up(n * 2 * sizeof(float), 256) + align_up(n * p.sectors * sizeof(float), 256) +
+    return align_up(n * 2 * sizeof(float), 256) + align_up(n * obs_dim_of(p) * sizeof(float), 256) +
            align_up(n * sizeof(float), 256);
 }
 
@@ -98,6 +98,7 @@ struct flock_server {
     char *arena = nullptr;
     size_t arena_bytes = 0;
     int max_slots = 0;
+    int layout_v = 0;             // sectors of every request (0 until the first submit)
     pol_t *pol = nullptr;
     hipStream_t stream = nullptr;
     ArenaAlloc alloc;
@@ -187,7 +188,7 @@ int try_admit(srv_t *S, Request &r) {
     r.act = reinterpret_cast<float *>(io);
     r.obs = reinterpret_cast<float *>(io + align_up(n * 2 * sizeof(float), 256));
     r.rew = reinterpret_cast<float *>(io + align_up(n * 2 * sizeof(float), 256) +
-                                      align_up(n * r.p.sectors * sizeof(float), 256));
+                                      align_up(n * obs_dim_of(r.p) * sizeof(float), 256));
     rc = env_load_host_state(r.env, r.x.data(), r.y.data(), r.th.data(), r.s.data(), S->stream);
     if (rc == ENV_OK) rc = env_reset(r.env, r.obs, S->stream);
     if (rc != ENV_OK) {
@@ -234,6 +235,10 @@ int rebuild_plan(srv_t *S) {
     S->plan.G = g;
     S->plan.C = c;
     S->plan.v = S->running.empty() ? 1 : S->reqs.at(S->running[0]).p.sectors;
+    S->plan.obs_dim = S->running.empty() ? 1 : obs_dim_of(S->reqs.at(S->running[0]).p);
+    S->plan.fov = 0;
+    for (int64_t rid : S->running)
+        if (!full_view(S->reqs.at(rid).p)) S->plan.fov = 1;
     S->plan.scan_blocks = scan_blocks_for(c);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)
@@ -293,15 +298,20 @@ int srv_submit(srv_t *S, const env_params_t *p, const float *x, const float *y, 
     if (!S || !id) return set_error(ENV_EINVAL, "NULL argument to srv_submit");
     int rc = validate_params(p);
     if (rc != ENV_OK) return rc;
-    if (p->sectors != policy_in_dim(S->pol))
-        return set_error(ENV_EINVAL, "request has %d sectors, policy takes %d", p->sectors,
-                         policy_in_dim(S->pol));
+    if (obs_dim_of(*p) != policy_in_dim(S->pol))
+        return set_error(ENV_EINVAL, "request observations have %d values, policy takes %d",
+                         obs_dim_of(*p), policy_in_dim(S->pol));
+    // Every request of a server shares one view layout: the first accepted fixes it.
+    if (S->layout_v != 0 && p->sectors != S->layout_v)
+        return set_error(ENV_EINVAL, "request has %d sectors, this server serves %d",
+                         p->sectors, S->layout_v);
     if (steps < 1) return set_error(ENV_EINVAL, "steps must be >= 1");
     const size_t n = (size_t)p->n_agents;
     if (n > 0 && (!x || !y || !th || !s)) return set_error(ENV_EINVAL, "state pointer is NULL");
     const size_t need = srv_request_bytes(p);
     if (need > S->arena_bytes)
         return set_error(ENV_ENOMEM, "request needs %zu bytes, arena has %zu", need, S->arena_bytes);
+    S->layout_v = p->sectors;
     Request r;
     r.id = S->next_id++;
     r.p = *p;

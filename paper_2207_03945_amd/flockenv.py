@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libflockenv.so")
 
 ENV_OK, ENV_EINVAL, ENV_ENOMEM, ENV_ESTATE, ENV_EHIP, ENV_EAGAIN, ENV_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 ENV_FLAG_COUNTS = 1
+ENV_FLAG_SPEED_OBS = 2
 
 _CODES = {ENV_EINVAL: "ENV_EINVAL", ENV_ENOMEM: "ENV_ENOMEM", ENV_ESTATE: "ENV_ESTATE",
           ENV_EHIP: "ENV_EHIP", ENV_EAGAIN: "ENV_EAGAIN", ENV_ENOTFOUND: "ENV_ENOTFOUND"}
@@ -34,7 +35,7 @@ class EnvParams(ctypes.Structure):
                 ("collide", ctypes.c_float), ("sectors", ctypes.c_int32), ("r_nb", ctypes.c_float),
                 ("r_col", ctypes.c_float), ("max_turn", ctypes.c_float),
                 ("max_dspeed", ctypes.c_float), ("s_min", ctypes.c_float), ("s_max", ctypes.c_float),
-                ("cell_reach", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("cell_reach", ctypes.c_int32), ("flags", ctypes.c_int32), ("fov", ctypes.c_float)]
 
 
 @dataclass
@@ -53,6 +54,12 @@ class Params:
     s_max: float = 2.0
     cell_reach: int = 0
     flags: int = 0
+    fov: float = 0.0   # view arc in radians; 0 = full circle
+
+    @property
+    def obs_dim(self) -> int:
+        """Length of a view row: the sectors, then the speed with ENV_FLAG_SPEED_OBS."""
+        return self.sectors + (1 if self.flags & ENV_FLAG_SPEED_OBS else 0)
 
     def c(self) -> EnvParams:
         return EnvParams(*[getattr(self, f.name) for f in fields(self)])
@@ -165,6 +172,7 @@ class Env:
         self.params = params
         self.n = params.n_agents
         self.v = params.sectors
+        self.d = params.obs_dim
         cp = params.c()
         nbytes = lib().env_workspace_bytes(ctypes.byref(cp))
         if nbytes == 0:
@@ -197,19 +205,19 @@ class Env:
 
     def reset(self, obs=None, stream=None):
         if obs is None:
-            obs = torch.empty(self.n, self.v, dtype=torch.float32, device=self.workspace.device)
-        _dev_f32(obs, (self.n, self.v), "obs")
+            obs = torch.empty(self.n, self.d, dtype=torch.float32, device=self.workspace.device)
+        _dev_f32(obs, (self.n, self.d), "obs")
         check(lib().env_reset(self.handle, _ptr(obs), _stream(stream)))
         return obs
 
     def step(self, act, obs=None, reward=None, stream=None):
         dev = self.workspace.device
         if obs is None:
-            obs = torch.empty(self.n, self.v, dtype=torch.float32, device=dev)
+            obs = torch.empty(self.n, self.d, dtype=torch.float32, device=dev)
         if reward is None:
             reward = torch.empty(self.n, dtype=torch.float32, device=dev)
         _dev_f32(act, (self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (self.n,), "reward")
         check(lib().env_step(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
         return obs, reward
@@ -248,6 +256,7 @@ class Batch:
         self.offsets = list(off)
         self.n = self.offsets[-1]
         self.v = self.envs[0].v
+        self.d = self.envs[0].d
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -257,14 +266,14 @@ class Batch:
 
     def step(self, act, obs, reward, stream=None):
         _dev_f32(act, (self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (self.n,), "reward")
         check(lib().env_step_batched(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
 
     def step_timed(self, act, obs, reward, stream=None):
         """One step; returns (move, scan, scatter, sweep) durations in ms (HIP events)."""
         _dev_f32(act, (self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (self.n,), "reward")
         ms = (ctypes.c_float * 4)()
         check(lib().env_step_batched_timed(self.handle, _ptr(act), _ptr(obs), _ptr(reward),
@@ -274,7 +283,7 @@ class Batch:
     def capture(self, k_steps, act, obs, reward, stream):
         """Capture the k-step graph ``run`` replays, without launching it."""
         _dev_f32(act, (k_steps, self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (k_steps, self.n), "reward")
         check(lib().env_batch_capture(self.handle, k_steps, _ptr(act), _ptr(obs), _ptr(reward),
                                       _stream(stream)))
@@ -282,14 +291,14 @@ class Batch:
     def run(self, k_steps, act, obs, reward, stream):
         """k_steps steps replayed from a HIP graph; ``stream`` must not be the null stream."""
         _dev_f32(act, (k_steps, self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (k_steps, self.n), "reward")
         check(lib().env_batch_run(self.handle, k_steps, _ptr(act), _ptr(obs), _ptr(reward),
                                   _stream(stream)))
 
     def step_policy(self, policy, act, obs, reward, stream=None):
         _dev_f32(act, (self.n, 2), "act")
-        _dev_f32(obs, (self.n, self.v), "obs")
+        _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (self.n,), "reward")
         check(lib().env_step_policy(self.handle, policy.handle, _ptr(act), _ptr(obs), _ptr(reward),
                                     _stream(stream)))

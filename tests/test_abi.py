@@ -8,6 +8,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -44,6 +45,7 @@ def _bytes(**kw):
     dict(collide=-0.1), dict(collide=9.0), dict(sectors=0), dict(sectors=257),
     dict(r_nb=math.nan), dict(max_turn=-0.1), dict(max_dspeed=math.inf), dict(s_min=-1.0),
     dict(s_min=3.0, s_max=2.0), dict(cell_reach=3), dict(cell_reach=-1), dict(flags=8),
+    dict(flags=4), dict(fov=-0.1), dict(fov=6.3), dict(fov=math.nan), dict(fov=math.inf),
 ])
 def test_invalid_params_rejected(kw):
     assert _bytes(**kw) == 0
@@ -52,7 +54,9 @@ def test_invalid_params_rejected(kw):
 
 @pytest.mark.parametrize("kw", [dict(), dict(n_agents=0), dict(sectors=1), dict(sectors=256),
                                 dict(radius=31.99), dict(collide=0.0), dict(cell_reach=2),
-                                dict(flags=1)])
+                                dict(flags=1), dict(flags=2), dict(flags=3),
+                                dict(fov=math.radians(250.0)), dict(fov=1e-3),
+                                dict(fov=float(np.float32(2 * math.pi)))])
 def test_valid_params_accepted(kw):
     assert _bytes(**kw) > 0
 
@@ -124,19 +128,26 @@ def test_batch_validation_without_gpu():
     assert lib.env_batch_workspace_bytes(pp, 2) == 0 and "sectors" in fe.last_error()
     b = ctypes.c_void_p()
     assert lib.env_batch_create(pp, 2, 1 << 20, 1 << 30, ctypes.byref(b)) == fe.ENV_EINVAL
+    rc3, h3, _ = _create(sectors=16, flags=fe.ENV_FLAG_SPEED_OBS)
+    arr[1] = h3.value
+    assert lib.env_batch_workspace_bytes(pp, 2) == 0 and "SPEED_OBS" in fe.last_error()
+    rc4, h4, _ = _create(sectors=16, fov=math.radians(250.0))
+    arr[1] = h4.value   # fields of view may differ within a batch
+    assert lib.env_batch_workspace_bytes(pp, 2) > 0
     arr[1] = h1.value
     assert lib.env_batch_workspace_bytes(pp, 2) > 0
     # envs not reset yet
     assert lib.env_batch_create(pp, 2, 1 << 20, 1 << 30, ctypes.byref(b)) == fe.ENV_ESTATE
-    lib.env_destroy(h1)
-    lib.env_destroy(h2)
+    for h in (h1, h2, h3, h4):
+        lib.env_destroy(h)
 
 
 def test_policy_and_server_validation_without_gpu():
     lib = fe.lib()
     assert lib.pol_workspace_bytes(16, 64) > 0
     assert lib.pol_workspace_bytes(32, 64) > lib.pol_workspace_bytes(16, 64)
-    for bad in ((0, 64), (33, 64), (16, 32)):
+    assert lib.pol_workspace_bytes(257, 64) > lib.pol_workspace_bytes(129, 64) > 0
+    for bad in ((0, 64), (258, 64), (16, 32)):
         assert lib.pol_workspace_bytes(*bad) == 0
     h = ctypes.c_void_p()
     assert lib.pol_create(None, 16, 64, 0.2, 0.1, 1 << 20, 1 << 20, None, ctypes.byref(h)) == fe.ENV_EINVAL
@@ -151,6 +162,12 @@ def test_policy_and_server_validation_without_gpu():
     small = fe.Params(n_agents=500, box=90.0)
     assert fe.request_bytes(p) > fe.request_bytes(small) > 0
     assert fe.request_bytes(fe.Params(n_agents=10, box=10.0)) == 0
+
+
+def test_obs_dim():
+    assert fe.Params(n_agents=4, box=64.0, sectors=128).obs_dim == 128
+    assert fe.Params(n_agents=4, box=64.0, sectors=128, flags=fe.ENV_FLAG_SPEED_OBS).obs_dim == 129
+    assert fe.Params(n_agents=4, box=64.0, flags=3).obs_dim == 17
 
 
 def test_missing_library_raises(tmp_path, monkeypatch):

@@ -44,7 +44,8 @@ def make_policy(in_dim, seed=0):
     return flock.Policy(ws, bs), ws, bs
 
 
-@pytest.mark.parametrize("in_dim,n", [(16, 4096), (16, 1), (16, 77), (8, 1000), (20, 333), (32, 64)])
+@pytest.mark.parametrize("in_dim,n", [(16, 4096), (16, 1), (16, 77), (8, 1000), (20, 333), (32, 64),
+                                      (33, 100), (48, 200), (128, 500), (129, 3000), (257, 64)])
 def test_policy_matches_fp64_within_bound(in_dim, n):
     pol, ws, bs = make_policy(in_dim)
     g = np.random.default_rng(in_dim * 1000 + n)

@@ -110,3 +110,27 @@ def test_slot_limit_and_errors():
     with pytest.raises(flock.FlockError) as ei:
         tiny.submit(*request(20000, seed=1), steps=3)
     assert ei.value.code == flock.flockenv.ENV_ENOMEM
+
+
+def test_paper_flock_requests_served_with_speed_view():
+    """129-input policy serving limited-view, speed-in-view requests; layouts are checked."""
+    ws, bs = workloads.xavier_weights([129, 64, 64, 2], seed=3)
+    pol = flock.Policy(ws, bs)
+    fov = math.radians(250.0)
+    p = flock.Params(n_agents=800, box=100.0, radius=10.0, sectors=128, fov=fov,
+                     flags=flock.ENV_FLAG_SPEED_OBS)
+    st = workloads.uniform_state(800, 100.0, seed=8)
+    srv = flock.Server(pol, 256 << 20, max_slots=4)
+    rid, _ = srv.submit(p, st, steps=6)
+    # same row length, other layout (129 sectors, no speed): rejected
+    with pytest.raises(flock.FlockError):
+        srv.submit(flock.Params(n_agents=100, box=100.0, radius=10.0, sectors=129),
+                   workloads.uniform_state(100, 100.0, seed=9), steps=3)
+    res, _ = drain(srv, [rid])
+    env = flock.Env(p)
+    env.set_state(*[torch.from_numpy(a).cuda() for a in st])
+    obs = env.reset()
+    for _ in range(6):
+        obs, _ = env.step(pol.forward(obs))
+    torch.cuda.synchronize()
+    assert np.array_equal(res[rid], env.returns().cpu().numpy())

@@ -385,3 +385,67 @@ def test_xavier_bounds_and_variance():
         if w.size > 1000:
             assert abs(w.var() - a * a / 3) < 0.1 * a * a / 3
     assert sum(w.size + b.size for w, b in zip(ws, bs)) == 5378
+
+
+# --------------------------------------------------------------------------- field of view
+
+FOV250 = math.radians(250.0)
+
+
+@pytest.mark.parametrize("bearing_deg,sector", [(180.0, -1), (100.0, 7), (-124.0, 0), (-126.0, -1),
+                                                (10.0, 4), (-10.0, 3), (124.0, 7), (126.0, -1)])
+def test_fov_two_agent(oracle_mod, bearing_deg, sector):
+    """250-degree view, 8 sectors of 31.25 degrees from the right edge (-125 deg)."""
+    d, heading = 3.0, 0.7
+    b = heading + math.radians(bearing_deg)
+    x = np.array([32.0, 32.0 + d * math.cos(b)], np.float32)
+    y = np.array([32.0, 32.0 + d * math.sin(b)], np.float32)
+    th = np.array([heading, 0.0], np.float32)
+    r = oracle_mod.oracle_sense(x, y, th, 64.0, sectors=8, agents=[0], fov=FOV250)
+    expect = np.zeros(8)
+    if sector >= 0:
+        expect[sector] = 1.0 - d / 8.0
+    np.testing.assert_allclose(r.obs[0], expect, rtol=0, atol=1e-6)
+    # the reward does not depend on the view (Eq. (1) sums over d < d_v)
+    assert r.n_nb[0] == 1 and abs(r.reward[0] - 0.1) < 1e-12
+
+
+def test_fov_coincident_is_straight_ahead(oracle_mod):
+    x = np.array([5.0, 5.0], np.float32)
+    th = np.array([2.0, 0.0], np.float32)
+    r = oracle_mod.oracle_sense(x, x.copy(), th, 64.0, sectors=8, agents=[0], fov=FOV250)
+    assert r.obs[0][4] == 1.0 and np.count_nonzero(r.obs[0]) == 1
+
+
+def test_half_view_equals_rotated_full_view(oracle_mod):
+    """A pi-wide view with 8 sectors is the first 8 of 16 full-view sectors
+    of the same agent turned by -pi/2 (the view's right edge)."""
+    n, box = 1500, 100.0
+    x, y, th, _ = workloads.uniform_state(n, box, seed=12)
+    half = oracle_mod.oracle_sense(x, y, th, box, sectors=8, fov=math.pi, eps_phi=1e-5)
+    th2 = np.mod(th.astype(np.float64) - math.pi / 2, 2 * math.pi).astype(np.float32)
+    full = oracle_mod.oracle_sense(x, y, th2, box, sectors=16, eps_phi=1e-5)
+    a, b = half.dmin_strict, full.dmin_strict[:, :8]
+    clean = (a == half.dmin_loose) & (b == full.dmin_loose[:, :8])
+    assert clean.mean() > 0.97
+    np.testing.assert_allclose(half.obs[clean], full.obs[:, :8][clean], rtol=0, atol=1e-12)
+    assert np.array_equal(half.n_nb, full.n_nb)
+
+
+def test_fov_only_hides_never_adds(oracle_mod):
+    n, box = 2000, 120.0
+    x, y, th, _ = workloads.uniform_state(n, box, seed=4)
+    full = oracle_mod.oracle_sense(x, y, th, box, sectors=16)
+    lim = oracle_mod.oracle_sense(x, y, th, box, sectors=16, fov=FOV250)
+    assert np.array_equal(full.reward, lim.reward)
+    # the nearest visible agent can never be nearer than the nearest agent
+    assert (lim.obs.max(axis=1) <= full.obs.max(axis=1) + 1e-15).all()
+    assert (lim.obs > 0).sum() < (full.obs > 0).sum()
+
+
+def test_observation_appends_speed(oracle_mod):
+    x, y, th, s = workloads.uniform_state(50, 40.0, seed=1)
+    s = (np.arange(50) * 0.03).astype(np.float32)
+    r = oracle_mod.oracle_sense(x, y, th, 40.0, sectors=8, agents=[3, 7])
+    o = oracle_mod.observation(r, s)
+    assert o.shape == (2, 9) and o[0, 8] == np.float32(0.09) and o[1, 8] == np.float32(0.21)

@@ -13,6 +13,10 @@ Workloads (all FP32, periodic square box of side L):
   * actions:  turn U[-0.2, 0.2] rad, dspeed U[-0.1, 0.1]
   * uneven env sizes: N_e = round(exp(U[ln lo, ln hi])), side L_e = 4 sqrt(N_e)
   * arrivals: Poisson process (exponential gaps) for the serving loop
+  * paper flock (Sec. 4.1, 5): v = 128 sectors, a field of view of 250
+    degrees, the speed appended to the view (129 values), vision range one
+    tenth of the box side; uniform start.  With R = L/10 the mean number of
+    neighbours is pi N / 100 whatever L, so only N sets the density.
 """
 from __future__ import annotations
 
@@ -125,6 +129,11 @@ WORKLOADS = {
     "blobs50k": dict(n=50000, box=1000.0, sectors=16, steps=500, init="blobs"),
     # 50,000 agents uniform, side 1,000 (control for the clustered case)
     "uniform50k": dict(n=50000, box=1000.0, sectors=16, steps=500, init="uniform"),
+    # the paper's own flock settings at 1,000 and 10,000 agents (box 100, R 10)
+    "paper_flock1k": dict(n=1000, box=100.0, radius=10.0, sectors=128, fov_deg=250.0,
+                          speed_obs=True, steps=128, init="uniform"),
+    "paper_flock10k": dict(n=10000, box=100.0, radius=10.0, sectors=128, fov_deg=250.0,
+                           speed_obs=True, steps=128, init="uniform"),
 }
 
 

@@ -307,6 +307,7 @@ def main():
 
     import paper_2207_03945_amd as flock
     import workloads
+    from paper_2207_03945_amd import autotune
 
     flock.lib()
     K, W = args.steps, args.warmup
@@ -318,6 +319,7 @@ def main():
     torch.cuda.synchronize()
     # barrier + synchronize bracket the timed region inside bench_batched
     main_res = bench_batched(flock, batch, K, W, seed=1)
+    main_res["sweep_lanes"] = batch.sweep_lanes
     G = batch.n
     del batch
     main_work = sweep_work(envs)
@@ -332,16 +334,18 @@ def main():
             plain = bench_plain(e50[0], 50000, K, W, seed=3)
             log(f"[bench] {name} batched x20")
             b50 = flock.Batch(e50)
+            lane_ms = autotune.time_sweep_lanes(b50, (1, 4, 16))
+            b50.set_sweep_lanes(min(lane_ms, key=lane_ms.get))
             bat = bench_batched(flock, b50, K, W, seed=4, timed_reps=10)
-            extra[name] = {"plain": plain, "batched_x20": bat}
+            extra[name] = {"plain": plain, "batched_x20": {**bat, "sweep_lanes": b50.sweep_lanes,
+                                                           "lanes_ms": lane_ms}}
             del b50, e50
         log("[bench] uneven 256 envs")
         ns, boxes = workloads.uneven_env_sizes(256, 100, 20000, seed=0)
         states = [workloads.uniform_state(int(n), float(b), seed=0, env=k)
                   for k, (n, b) in enumerate(zip(ns, boxes))]
         plist = [flock.Params(n_agents=int(n), box=float(b), sectors=V) for n, b in zip(ns, boxes)]
-        from paper_2207_03945_amd import autotune
-        reach, tune_ms = autotune.tune_reach(plist, states, cache=None)
+        reach, lanes, tune_ms = autotune.tune(plist, states, cache=None)
         envs_u = []
         for p_, st in zip(plist, states):
             p_.cell_reach = reach
@@ -350,23 +354,31 @@ def main():
             e.reset()
             envs_u.append(e)
         bu = flock.Batch(envs_u)
-        extra["uneven256"] = {"agents": bu.n, "cell_reach": reach,
-                              "tuned_ms": {str(k): v for k, v in tune_ms.items()},
+        bu.set_sweep_lanes(lanes)
+        extra["uneven256"] = {"agents": bu.n, "cell_reach": reach, "sweep_lanes": lanes,
+                              "tuned_ms": tune_ms,
                               **bench_batched(flock, bu, K, W, seed=5, timed_reps=10)}
         del bu, envs_u
         log("[bench] paper flock 10k")
         pf = workloads.WORKLOADS["paper_flock10k"]
         pf_params = dict(sectors=pf["sectors"], radius=pf["radius"],
                          fov=math.radians(pf["fov_deg"]), flags=flock.ENV_FLAG_SPEED_OBS)
-        e10 = make_envs(flock, workloads, pf["n"], pf["box"], 20, "uniform", 3000, **pf_params)
+        pf_plist = [flock.Params(n_agents=pf["n"], box=pf["box"], **pf_params) for _ in range(20)]
+        pf_states = [workloads.uniform_state(pf["n"], pf["box"], seed=3000 + k) for k in range(20)]
+        pf_reach, pf_lanes, pf_ms = autotune.tune(pf_plist, pf_states, cache=None)
+        e10 = make_envs(flock, workloads, pf["n"], pf["box"], 20, "uniform", 3000,
+                        cell_reach=pf_reach, **pf_params)
+        e10[0].set_sweep_lanes(pf_lanes)
         plain = bench_plain(e10[0], pf["n"], K, W, seed=6)
         b10 = flock.Batch(e10)
+        b10.set_sweep_lanes(pf_lanes)
         bat = bench_batched(flock, b10, K, W, seed=7, timed_reps=10)
         work = sweep_work(e10)
         pf_bytes = 8 + 4 + 4 * (pf["sectors"] + 1) + 4 + 16
         extra["paper_flock10k"] = {
             "workload": "20 envs x 10,000 agents, side 100, vision 10 (L/10), 128 sectors, "
                         "field of view 250 degrees, speed appended (129 values)",
+            "cell_reach": pf_reach, "sweep_lanes": pf_lanes, "tuned_ms": pf_ms,
             "plain": plain, "batched_x20": bat, "sweep_work_per_launch": work,
             "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"]),
             "sweep_hbm_frac": pf_bytes * b10.n / (bat["phase_ms"]["sweep"] * 1e-3) / HBM_PEAK}

@@ -127,6 +127,14 @@ void env_destroy(env_t *env);
 /* Effective cell grid: cells per side (1 = all-pairs), reach, cell side. */
 int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell);
 
+/* Lanes of the neighbour sweep that share one agent's candidates (a lane
+ * group inside a wavefront): 1, 4, 16 or 64, or 0 to choose from the
+ * expected candidates per agent (about (2 cell_reach + 1)^2 n / ncell^2).
+ * Results do not depend on it; sparse neighbourhoods favour 1, dense ones
+ * (hundreds of candidates per agent) larger groups.  ENV_EINVAL for other
+ * values. */
+int env_set_sweep_lanes(env_t *env, int lanes);
+
 /* Copy a state in (device x, y, th, s, each [n] FP32).  Values must already
  * lie in their ranges (positions in [0, box), heading in [0, 2pi)); they are
  * not checked.  Enqueued on `stream`. */
@@ -171,6 +179,13 @@ size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs);
 int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes,
                      env_batch_t **out);
 void env_batch_destroy(env_batch_t *b);
+
+/* As env_set_sweep_lanes, for the batched step (0 = chosen from the
+ * agent-weighted mean of the envs' expected candidates).  Drops captured
+ * graphs when the choice changes. */
+int env_batch_set_sweep_lanes(env_batch_t *b, int lanes);
+/* *lanes receives the lanes per agent the batched sweep uses now. */
+int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes);
 
 /* off[n_envs + 1] (host) receives the row offsets described above. */
 int env_batch_offsets(const env_batch_t *b, int64_t *off);

@@ -71,6 +71,8 @@ int check_params(const env_params_t *p) {
 }
 
 
+bool valid_lanes(int lanes) { return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64; }
+
 struct Geometry {
     int ncell, reach;
     float cell, inv_cell;
@@ -254,6 +256,24 @@ DevEnv env_descriptor(const env_t *env, int flip) { return orient(env, env->pari
 
 int64_t env_cell_count(const env_t *env) { return (int64_t)env->gm.ncell * env->gm.ncell; }
 
+double env_candidates_per_agent(const env_t *env) {
+    const double n = env->p.n_agents;
+    if (env->gm.ncell == 1) return n;
+    const double w = 2.0 * env->gm.reach + 1.0, nc = env->gm.ncell;
+    return n * w * w / (nc * nc);
+}
+
+// One lane per agent suits a few dozen candidates.  Beyond that a lane group
+// per agent keeps the lanes busy; with many sectors (v > 32) one lane per
+// agent also needs v words of LDS per lane, which caps occupancy, so groups
+// of 16 win early.  Measured on MI355X: 30 candidates, v = 16 -> 1;
+// ~500, v = 16 -> 4; 111 and 1,111, v = 128 -> 16.
+int auto_lanes(double cand, int v) {
+    if (cand < 64.0) return 1;
+    if (v > 32) return 16;
+    return cand < 1024.0 ? 4 : 16;
+}
+
 const env_params_t &env_params(const env_t *env) { return env->p; }
 
 int env_parity(const env_t *env) { return env->parity; }
@@ -334,6 +354,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.v = p->sectors;
     e->plan.obs_dim = obs_dim_of(*p);
     e->plan.fov = full_view(*p) ? 0 : 1;
+    e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors);
     e->plan.scan_blocks = scan_blocks_for(e->plan.C);
     *out = e;
     g_err.clear();
@@ -347,6 +368,13 @@ int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell) 
     if (ncell) *ncell = env->gm.ncell;
     if (reach) *reach = env->gm.reach;
     if (cell) *cell = env->gm.cell;
+    return ENV_OK;
+}
+
+int env_set_sweep_lanes(env_t *env, int lanes) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (lanes != 0 && !valid_lanes(lanes)) return fail(ENV_EINVAL, "lanes must be 0, 1, 4, 16 or 64");
+    env->plan.lanes = lanes ? lanes : auto_lanes(env_candidates_per_agent(env), env->p.sectors);
     return ENV_OK;
 }
 
@@ -462,6 +490,15 @@ size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs) {
     return sort_scratch_bytes(G, C, n_envs);
 }
 
+static int batch_auto_lanes(const std::vector<env_t *> &envs) {
+    double cand = 0.0, n = 0.0;
+    for (const env_t *e : envs) {
+        cand += env_candidates_per_agent(e) * e->p.n_agents;
+        n += e->p.n_agents;
+    }
+    return auto_lanes(n > 0.0 ? cand / n : 0.0, envs.empty() ? 1 : envs[0]->p.sectors);
+}
+
 int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env_batch_t **out) {
     if (!out) return fail(ENV_EINVAL, "out is NULL");
     if (!ws) return fail(ENV_EINVAL, "workspace is NULL");
@@ -496,6 +533,7 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.v = v;
     b->plan.obs_dim = obs_dim;
     b->plan.fov = fov;
+    b->plan.lanes = batch_auto_lanes(b->envs);
     b->plan.scan_blocks = scan_blocks_for(C);
     *out = b;
     return ENV_OK;
@@ -515,6 +553,23 @@ void env_batch_destroy(env_batch_t *b) {
     for (auto &ev : b->events)
         if (ev) (void)hipEventDestroy(ev);
     delete b;
+}
+
+int env_batch_set_sweep_lanes(env_batch_t *b, int lanes) {
+    if (!b) return fail(ENV_EINVAL, "batch is NULL");
+    if (lanes != 0 && !valid_lanes(lanes)) return fail(ENV_EINVAL, "lanes must be 0, 1, 4, 16 or 64");
+    const int want = lanes ? lanes : batch_auto_lanes(b->envs);
+    if (want != b->plan.lanes) {
+        drop_graphs(b);
+        b->plan.lanes = want;
+    }
+    return ENV_OK;
+}
+
+int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes) {
+    if (!b || !lanes) return fail(ENV_EINVAL, "NULL argument");
+    *lanes = b->plan.lanes;
+    return ENV_OK;
 }
 
 int env_batch_offsets(const env_batch_t *b, int64_t *off) {

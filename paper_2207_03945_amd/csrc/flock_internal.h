@@ -74,6 +74,7 @@ struct StepPlan {
     int v;        // sectors
     int obs_dim;  // view row length: v, or v + 1 with the speed appended
     int fov;      // any env of the plan has a limited view
+    int lanes;    // lanes per agent in the sweep: 1, 4, 16 or 64
     int scan_blocks;  // 0 -> single-block scan
 };
 
@@ -125,6 +126,10 @@ hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStrea
 int validate_params(const env_params_t *p);     // ENV_OK or ENV_EINVAL (+ message)
 bool full_view(const env_params_t &p);          // fov 0 or 2 pi: the whole circle
 int obs_dim_of(const env_params_t &p);          // view row length: sectors (+ 1 for speed)
+// Expected candidate tests per agent of an env (uniform density over its grid).
+double env_candidates_per_agent(const env_t *env);
+// Sweep lanes per agent for a mean of `cand` candidate tests per agent, v sectors.
+int auto_lanes(double cand, int v);
 // Descriptor with agent_base = cell_base = 0, oriented so that rec_cur is
 // the env's current buffer (flip = 1 swaps cur and nxt).
 DevEnv env_descriptor(const env_t *env, int flip);

@@ -430,15 +430,16 @@ struct ViewK {
 
 // Test candidates [q, q1) against the lane's agent: distance test, and for a
 // neighbour the count, the collision count and the per-sector minimum (an
-// LDS atomic min on the lane's own slot).  The sector is computed for every
-// candidate (branch-free); only the LDS update is predicated.  (offx, xi),
-// (offy, yi): candidate shift (0 or -L) and centre (x or x - L) per axis;
-// minimg selects the per-candidate minimum image (single-cell envs).
-// kFov selects the limited-view sector (candidates outside the arc are
-// counted but update no sector).
-template <int NT, int UNROLL, bool kFov>
+// LDS atomic min on the agent's own minima, S words apart).  The sector is
+// computed for every candidate (branch-free); only the LDS update is
+// predicated.  With G lanes per agent, lane li takes candidates q + li,
+// q + li + G, ...  (offx, xi), (offy, yi): candidate shift (0 or -L) and
+// centre (x or x - L) per axis; minimg selects the per-candidate minimum
+// image (single-cell envs).  kFov selects the limited-view sector
+// (candidates outside the arc are counted but update no sector).
+template <int S, int G, int UNROLL, bool kFov>
 __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
-                                          int q, int q1, int self, float offx, float xi,
+                                          int q, int q1, int li, int self, float offx, float xi,
                                           float offy, float yi, bool minimg, float L, float r2,
                                           float c2, const ViewK &K, int &nb, int &col) {
     auto test = [&](const float2 pj, int qq) {
@@ -456,103 +457,133 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
         col += (nbr && d2 < c2) ? 1 : 0;
         if (kFov) {
             const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
-            if (nbr && k >= 0) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+            if (nbr && k >= 0) atomicMin(&smin_own[k * S], __float_as_uint(d2));
         } else {
             const int k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
-            if (nbr) atomicMin(&smin_own[k * NT], __float_as_uint(d2));
+            if (nbr) atomicMin(&smin_own[k * S], __float_as_uint(d2));
         }
     };
-    for (; q + UNROLL <= q1; q += UNROLL) {
+    q += li;
+    for (; q + (UNROLL - 1) * G < q1; q += UNROLL * G) {
         float2 pj[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) pj[u] = sxy[q + u];
+        for (int u = 0; u < UNROLL; ++u) pj[u] = sxy[q + u * G];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) test(pj[u], q + u);
+        for (int u = 0; u < UNROLL; ++u) test(pj[u], q + u * G);
     }
-    for (; q < q1; ++q) test(sxy[q], q);
+    for (; q < q1; q += G) test(sxy[q], q);
 }
 
 // Candidates per loop iteration of the sweep (independent loads in flight).
 constexpr int kUnroll = 4;
 
-// NT threads per block, one agent (in the new cell order) per thread; the
-// per-thread sector minima take v * NT * 4 bytes of dynamic LDS.
+// NT threads per block, G lanes per agent (in the new cell order): A = NT/G
+// agents per block, their sector minima v * A * 4 bytes of dynamic LDS.  G = 1
+// suits sparse neighbourhoods (a few dozen candidates); dense ones (hundreds
+// to thousands of candidates per agent) share each agent's candidate runs
+// among a lane group, which keeps the lanes busy and the LDS per agent small.
 // kFov: some env of the launch has a limited field of view.  obs rows hold
 // obs_dim floats: the v sectors, then the speed when obs_dim > v.
-template <int NT, bool kFov>
+template <int NT, int G, bool kFov>
 __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
-                                              int n_envs, int G, int v, int obs_dim,
+                                              int n_envs, int Gtot, int v, int obs_dim,
                                               float *__restrict__ obs, float *__restrict__ reward,
                                               int add_ret) {
-    extern __shared__ uint32_t s_min[];  // [v][NT]
+    constexpr int A = NT / G;
+    extern __shared__ uint32_t s_min[];  // [v][A]
     __shared__ int s_env;
-    const int p0 = blockIdx.x * NT;
-    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    const int tid = threadIdx.x, slot = tid / G, li = tid % G;
+    const int p0 = blockIdx.x * A;
+    if (tid == 0) s_env = env_search(a.base, n_envs, p0);
+    uint32_t *smin = s_min + slot;
+    if constexpr (G > 1)
+        for (int k = li; k < v; k += G) smin[k * A] = kInfBits;
     __syncthreads();
-    const int tid = threadIdx.x;
-    const int pos = p0 + tid;
-    if (pos >= G) return;
+    const int pos = p0 + slot;
+    if constexpr (G == 1) {
+        if (pos >= Gtot) return;
+    }
+    // G > 1: every lane reaches the second barrier; a group is active or not as a whole
+    const bool active = pos < Gtot;
     int e = s_env;
-    while (a.base[e + 1] <= pos) ++e;
+    if (active)
+        while (a.base[e + 1] <= pos) ++e;
     const DevEnv &E = envs[e];
     const int j = pos - E.agent_base;
-    const float4 me = E.rec_nxt[j];
-    double sd, cd;
-    sincos((double)me.z, &sd, &cd);
-    const float c = (float)cd, s = (float)sd;
-    uint32_t *smin = s_min + tid;
-    for (int k = 0; k < v; ++k) smin[k * NT] = kInfBits;
-
-    const ViewK K{c, s, E.fov_half, E.fov_t, E.sec_scale, (float)v, v};
-    const float L = E.box, r2 = E.r2, c2 = E.c2;
-    const int ncell = E.ncell, cb = E.cell_base;
+    float4 me = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     int nb = 0, col = 0;
-    if (ncell == 1) {
-        sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[cb], a.start[cb + 1], pos, 0.0f, me.x, 0.0f,
-                               me.y, true, L, r2, c2, K, nb, col);
-    } else {
-        const int reach = E.reach;
-        const int cx = cell_of(me.x, E.inv_cell, ncell);
-        const int cy = cell_of(me.y, E.inv_cell, ncell);
-        const int lo = cy - reach, hi = cy + reach;
-        for (int ox = -reach; ox <= reach; ++ox) {
-            int ccx = cx + ox;
-            float offx = 0.0f, xi = me.x;
-            if (ccx < 0) {
-                ccx += ncell;
-                offx = -L;
-            } else if (ccx >= ncell) {
-                ccx -= ncell;
-                xi = me.x - L;
-            }
-            const int colb = cb + ccx * ncell;
-            if (lo < 0) {
-                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
-                                       pos, offx, xi, -L, me.y, false, L, r2, c2, K, nb, col);
-                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], pos, offx,
-                                       xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
-            } else if (hi >= ncell) {
-                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], pos,
-                                       offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
-                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
-                                       pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, K, nb, col);
-            } else {
-                sweep_run<NT, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], pos,
-                                       offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+    if (active) {
+        me = E.rec_nxt[j];
+        double sd, cd;
+        sincos((double)me.z, &sd, &cd);
+        const float c = (float)cd, s = (float)sd;
+        if constexpr (G == 1)
+            for (int k = 0; k < v; ++k) smin[k * A] = kInfBits;
+
+        const ViewK K{c, s, E.fov_half, E.fov_t, E.sec_scale, (float)v, v};
+        const float L = E.box, r2 = E.r2, c2 = E.c2;
+        const int ncell = E.ncell, cb = E.cell_base;
+        if (ncell == 1) {
+            sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[cb], a.start[cb + 1], li, pos, 0.0f, me.x, 0.0f,
+                                   me.y, true, L, r2, c2, K, nb, col);
+        } else {
+            const int reach = E.reach;
+            const int cx = cell_of(me.x, E.inv_cell, ncell);
+            const int cy = cell_of(me.y, E.inv_cell, ncell);
+            const int lo = cy - reach, hi = cy + reach;
+            for (int ox = -reach; ox <= reach; ++ox) {
+                int ccx = cx + ox;
+                float offx = 0.0f, xi = me.x;
+                if (ccx < 0) {
+                    ccx += ncell;
+                    offx = -L;
+                } else if (ccx >= ncell) {
+                    ccx -= ncell;
+                    xi = me.x - L;
+                }
+                const int colb = cb + ccx * ncell;
+                if (lo < 0) {
+                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
+                                           li, pos, offx, xi, -L, me.y, false, L, r2, c2, K, nb, col);
+                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], li, pos, offx,
+                                           xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                } else if (hi >= ncell) {
+                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], li, pos,
+                                           offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
+                                           li, pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, K, nb, col);
+                } else {
+                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], li, pos,
+                                           offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                }
             }
         }
-    }
+    }  // active
 
+    if constexpr (G > 1) {
+        __syncthreads();  // the group's minima are complete
+        if (!active) return;
+#pragma unroll
+        for (int m = G / 2; m >= 1; m >>= 1) {
+            nb += __shfl_xor(nb, m, 64);
+            col += __shfl_xor(col, m, 64);
+        }
+    }
     const int id = E.id_nxt[j];
     const float inv_r = E.inv_radius;
     float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
-    if (obs_dim > v) orow[v] = me.w;  // speed after the move (Sec. 4.1)
-    if ((obs_dim & 3) == 0 && (v & 3) == 0) {
+    if (li == 0 && obs_dim > v) orow[v] = me.w;  // speed after the move (Sec. 4.1)
+    if constexpr (G > 1) {
+        for (int k = li; k < v; k += G) {
+            const uint32_t m = smin[k * A];
+            orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
+        }
+    } else if ((obs_dim & 3) == 0 && (v & 3) == 0) {
         for (int k = 0; k < v; k += 4) {
             float o[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t m = smin[(k + u) * NT];
+                const uint32_t m = smin[(k + u) * A];
                 o[u] = m == kInfBits ? 0.0f
                                      : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
             }
@@ -560,10 +591,11 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         }
     } else {
         for (int k = 0; k < v; ++k) {
-            const uint32_t m = smin[k * NT];
+            const uint32_t m = smin[k * A];
             orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
         }
     }
+    if (li != 0) return;
     const float r = E.r_nb * (float)nb + E.r_col * (float)col;
     if (reward) reward[E.agent_base + id] = r;
     else if (E.rew) E.rew[id] = r;
@@ -645,6 +677,22 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+template <int NT, int G>
+void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
+                  int add_return, hipStream_t s) {
+    constexpr int A = NT / G;
+    const size_t lds = (size_t)p.v * A * sizeof(uint32_t);
+    const dim3 grid(blocks_for(Gtot, A));
+    if (p.fov)
+        hipLaunchKernelGGL((k_sweep<NT, G, true>), grid, dim3(NT), lds, s, p.a, envs, p.n_envs, Gtot,
+                           p.v, p.obs_dim, obs, reward, add_return);
+    else
+        hipLaunchKernelGGL((k_sweep<NT, G, false>), grid, dim3(NT), lds, s, p.a, envs, p.n_envs,
+                           Gtot, p.v, p.obs_dim, obs, reward, add_return);
+}
+}  // namespace
+
 hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
                        float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
     if (p.G == 0) return hipSuccess;
@@ -666,23 +714,12 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
     if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G);
     if (ev) (void)hipEventRecord(ev[3], s);
-    if (p.v <= 32) {
-        const size_t lds = (size_t)p.v * 256 * sizeof(uint32_t);
-        if (p.fov)
-            hipLaunchKernelGGL((k_sweep<256, true>), dim3(blocks_for(G, 256)), dim3(256), lds, s,
-                               p.a, envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
-        else
-            hipLaunchKernelGGL((k_sweep<256, false>), dim3(blocks_for(G, 256)), dim3(256), lds, s,
-                               p.a, envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
-    } else {
-        const size_t lds = (size_t)p.v * 64 * sizeof(uint32_t);
-        if (p.fov)
-            hipLaunchKernelGGL((k_sweep<64, true>), dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a,
-                               envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
-        else
-            hipLaunchKernelGGL((k_sweep<64, false>), dim3(blocks_for(G, 64)), dim3(64), lds, s, p.a,
-                               envs, p.n_envs, G, p.v, p.obs_dim, obs, reward, add_return);
-    }
+    const int lanes = p.lanes;
+    if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s);
+    else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s);
+    else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s);
+    else if (p.v <= 32) launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
+    else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s);
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }

@@ -237,8 +237,13 @@ int rebuild_plan(srv_t *S) {
     S->plan.v = S->running.empty() ? 1 : S->reqs.at(S->running[0]).p.sectors;
     S->plan.obs_dim = S->running.empty() ? 1 : obs_dim_of(S->reqs.at(S->running[0]).p);
     S->plan.fov = 0;
-    for (int64_t rid : S->running)
-        if (!full_view(S->reqs.at(rid).p)) S->plan.fov = 1;
+    double cand = 0.0;
+    for (int64_t rid : S->running) {
+        const Request &r = S->reqs.at(rid);
+        if (!full_view(r.p)) S->plan.fov = 1;
+        cand += env_candidates_per_agent(r.env) * r.p.n_agents;
+    }
+    S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v);
     S->plan.scan_blocks = scan_blocks_for(c);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)

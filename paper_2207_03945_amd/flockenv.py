@@ -98,6 +98,9 @@ def lib():
         "env_batch_create": (ctypes.c_int, [_PP, ctypes.c_int, _P, ctypes.c_size_t, _PP]),
         "env_batch_destroy": (None, [_P]),
         "env_batch_offsets": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "env_set_sweep_lanes": (ctypes.c_int, [_P, ctypes.c_int]),
+        "env_batch_set_sweep_lanes": (ctypes.c_int, [_P, ctypes.c_int]),
+        "env_batch_get_sweep_lanes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "env_step_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_batch_run": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
         "env_batch_capture": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
@@ -193,6 +196,10 @@ class Env:
         check(lib().env_geometry(self.handle, ctypes.byref(nc), ctypes.byref(r), ctypes.byref(c)))
         return nc.value, r.value, c.value
 
+    def set_sweep_lanes(self, lanes: int):
+        """Lanes per agent in the neighbour sweep (1, 4, 16, 64; 0 = automatic)."""
+        check(lib().env_set_sweep_lanes(self.handle, int(lanes)))
+
     def set_state(self, x, y, th, s, stream=None):
         for t, nm in ((x, "x"), (y, "y"), (th, "th"), (s, "s")):
             _dev_f32(t, (self.n,), nm)
@@ -263,6 +270,16 @@ class Batch:
         if h is not None and _lib is not None:
             _lib.env_batch_destroy(h)
             self.handle = None
+
+    def set_sweep_lanes(self, lanes: int):
+        """Lanes per agent in the batched sweep (1, 4, 16, 64; 0 = automatic)."""
+        check(lib().env_batch_set_sweep_lanes(self.handle, int(lanes)))
+
+    @property
+    def sweep_lanes(self) -> int:
+        v = ctypes.c_int32()
+        check(lib().env_batch_get_sweep_lanes(self.handle, ctypes.byref(v)))
+        return v.value
 
     def step(self, act, obs, reward, stream=None):
         _dev_f32(act, (self.n, 2), "act")

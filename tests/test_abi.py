@@ -164,6 +164,19 @@ def test_policy_and_server_validation_without_gpu():
     assert fe.request_bytes(fe.Params(n_agents=10, box=10.0)) == 0
 
 
+def test_sweep_lanes_validation_without_gpu():
+    lib = fe.lib()
+    rc, h, _ = _create()
+    assert rc == fe.ENV_OK
+    for bad in (2, 3, 8, 128, -1):
+        assert lib.env_set_sweep_lanes(h, bad) == fe.ENV_EINVAL
+    for ok in (0, 1, 4, 16, 64):
+        assert lib.env_set_sweep_lanes(h, ok) == fe.ENV_OK
+    assert lib.env_set_sweep_lanes(None, 1) == fe.ENV_EINVAL
+    assert lib.env_batch_set_sweep_lanes(None, 1) == fe.ENV_EINVAL
+    lib.env_destroy(h)
+
+
 def test_obs_dim():
     assert fe.Params(n_agents=4, box=64.0, sectors=128).obs_dim == 128
     assert fe.Params(n_agents=4, box=64.0, sectors=128, flags=fe.ENV_FLAG_SPEED_OBS).obs_dim == 129

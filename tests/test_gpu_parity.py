@@ -269,6 +269,51 @@ def test_batched_equals_plain_bitwise():
             assert torch.equal(u, w)
 
 
+@pytest.mark.parametrize("lanes", [4, 16, 64])
+def test_sweep_lane_groups_bitwise_equal_to_one_lane(lanes):
+    """Lane groups per agent give the same bits as one lane per agent.
+
+    Envs: 50,000 agents in 64 blobs (hundreds of candidates per agent), a
+    dense uniform env, a single-cell env, a reach-2 env, three tiny ones and
+    an empty one, batched; the one-lane reference is each env stepped alone.
+    """
+    specs = [(50000, 1000.0, 0, "blobs"), (4000, 100.0, 0, "uniform"), (150, 20.0, 0, "uniform"),
+             (800, 100.0, 2, "uniform"), (1, 64.0, 0, "uniform"), (2, 64.0, 0, "uniform"),
+             (3, 30.0, 0, "uniform"), (0, 64.0, 0, "uniform")]
+    states, ref, grp = [], [], []
+    for k, (n, box, reach, init) in enumerate(specs):
+        st = (workloads.blob_state(n, box, seed=k) if init == "blobs"
+              else workloads.uniform_state(n, box, seed=k))
+        states.append(st)
+        e1 = make_env(st, box, 16, reach=reach)[0]
+        e1.set_sweep_lanes(1)
+        ref.append(e1)
+        grp.append(make_env(st, box, 16, reach=reach)[0])
+    batch = flock.Batch(grp)
+    batch.set_sweep_lanes(lanes)
+    G, off = batch.n, batch.offsets
+    obs_b = torch.empty(G, 16, device="cuda")
+    rew_b = torch.empty(G, device="cuda")
+    for t in range(3):
+        acts = [workloads.random_actions(st[0].shape[0], seed=2, step=t, env=k)
+                for k, st in enumerate(states)]
+        batch.step(dev(np.concatenate(acts).reshape(G, 2)), obs_b, rew_b)
+        for k, env in enumerate(ref):
+            o, r = env.step(dev(acts[k]))
+            assert torch.equal(o, obs_b[off[k]:off[k + 1]]), f"obs env {k} step {t}"
+            assert torch.equal(r, rew_b[off[k]:off[k + 1]]), f"reward env {k} step {t}"
+    for ea, eb in zip(ref, grp):
+        assert torch.equal(ea.returns(), eb.returns())
+        assert all(torch.equal(u, w) for u, w in zip(ea.counts(), eb.counts()))
+    # and against the oracle on sampled agents of the clustered env
+    st = states[0]
+    for t in range(3):
+        st = oracle.oracle_move(st, workloads.random_actions(50000, seed=2, step=t, env=0), 1000.0)
+    agents = np.sort(np.random.default_rng(lanes).choice(50000, 1500, replace=False)).astype(np.int32)
+    check_step(grp[0], st, 1000.0, 16, obs_b[off[0]:off[1]], rew_b[off[0]:off[1]], agents=agents,
+               label=f"lanes {lanes}")
+
+
 def test_batched_uneven_256_envs_against_oracle():
     """256 envs, N_e log-uniform in [100, 20,000] at density 1/16: sampled agents per env."""
     ns, boxes, states = _uneven(256, 100, 20000, seed=0)

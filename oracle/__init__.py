@@ -6,10 +6,13 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 
 ``oracle_move`` / ``oracle_sense`` are thin ctypes wrappers round the plain C
 in ``flock_oracle.c`` (all-pairs, double-precision sensing).  ``policy_forward``
-is the double-precision policy network in ``policy.py``.
+is the double-precision policy network in ``policy.py``; ``rl.py`` holds the
+experience-collection pieces (Gaussian action sampling, the critic, the
+truncated advantage estimator).
 
 Parity pins: every function here is pinned by ``tests/test_oracle_pins.py``
-against closed forms, brute-force lattice counts, invariants and statistics.
+and ``tests/test_oracle_rl_pins.py`` against closed forms, brute-force lattice
+counts, invariants, statistics and library densities.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import subprocess
 
 import numpy as np
 
+from . import rl  # noqa: F401
 from .policy import policy_forward, xavier_limits  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

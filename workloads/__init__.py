@@ -13,6 +13,7 @@ Workloads (all FP32, periodic square box of side L):
   * actions:  turn U[-0.2, 0.2] rad, dspeed U[-0.1, 0.1]
   * uneven env sizes: N_e = round(exp(U[ln lo, ln hi])), side L_e = 4 sqrt(N_e)
   * arrivals: Poisson process (exponential gaps) for the serving loop
+  * policy noise: standard normals [steps, n, 2] for Gaussian action sampling
   * paper flock (Sec. 4.1, 5): v = 128 sectors, a field of view of 250
     degrees, the speed appended to the view (129 values), vision range one
     tenth of the box side; uniform start.  With R = L/10 the mean number of
@@ -30,6 +31,7 @@ PURPOSE_WEIGHTS = 3
 PURPOSE_SIZES = 4
 PURPOSE_ARRIVALS = 5
 PURPOSE_BLOB_CENTRES = 6
+PURPOSE_POLICY_NOISE = 7
 
 
 def rng(seed: int, purpose: int, env: int = 0, step: int = 0) -> np.random.Generator:
@@ -105,6 +107,12 @@ def xavier_weights(dims, seed: int = 0):
         ws.append(((g.random((fi, fo)) * 2.0 - 1.0) * a).astype(np.float32))
         bs.append(np.zeros(fo, np.float32))
     return ws, bs
+
+
+def policy_noise(steps: int, n: int, seed: int = 0, env: int = 0) -> np.ndarray:
+    """Standard-normal draws [steps, n, 2] (FP32) for sampling actions round the policy mean."""
+    g = rng(seed, PURPOSE_POLICY_NOISE, env)
+    return g.standard_normal((steps, n, 2)).astype(np.float32)
 
 
 def poisson_arrivals(rate: float, duration: float, seed: int = 0):

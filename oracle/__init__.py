@@ -8,10 +8,12 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 in ``flock_oracle.c`` (all-pairs, double-precision sensing).  ``policy_forward``
 is the double-precision policy network in ``policy.py``; ``rl.py`` holds the
 experience-collection pieces (Gaussian action sampling, the critic, the
-truncated advantage estimator).
+truncated advantage estimator); ``graph.py`` the opinion-dynamics graph
+interaction.
 
 Parity pins: every function here is pinned by ``tests/test_oracle_pins.py``
-and ``tests/test_oracle_rl_pins.py`` against closed forms, brute-force lattice
+``tests/test_oracle_rl_pins.py`` and ``tests/test_oracle_graph_pins.py``
+against closed forms, brute-force lattice
 counts, invariants, statistics and library densities.
 """
 from __future__ import annotations
@@ -23,7 +25,7 @@ import subprocess
 
 import numpy as np
 
-from . import rl  # noqa: F401
+from . import graph, rl  # noqa: F401
 from .policy import policy_forward, xavier_limits  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

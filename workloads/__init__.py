@@ -14,6 +14,8 @@ Workloads (all FP32, periodic square box of side L):
   * uneven env sizes: N_e = round(exp(U[ln lo, ln hi])), side L_e = 4 sqrt(N_e)
   * arrivals: Poisson process (exponential gaps) for the serving loop
   * policy noise: standard normals [steps, n, 2] for Gaussian action sampling
+  * social graph: power-law degrees (exponent 2.5, 5..2,000, mean about 14),
+    configuration-model pairing, symmetric weights U[0, 1), opinions U[0, 1)
   * paper flock (Sec. 4.1, 5): v = 128 sectors, a field of view of 250
     degrees, the speed appended to the view (129 values), vision range one
     tenth of the box side; uniform start.  With R = L/10 the mean number of
@@ -32,6 +34,7 @@ PURPOSE_SIZES = 4
 PURPOSE_ARRIVALS = 5
 PURPOSE_BLOB_CENTRES = 6
 PURPOSE_POLICY_NOISE = 7
+PURPOSE_GRAPH = 8
 
 
 def rng(seed: int, purpose: int, env: int = 0, step: int = 0) -> np.random.Generator:
@@ -113,6 +116,42 @@ def policy_noise(steps: int, n: int, seed: int = 0, env: int = 0) -> np.ndarray:
     """Standard-normal draws [steps, n, 2] (FP32) for sampling actions round the policy mean."""
     g = rng(seed, PURPOSE_POLICY_NOISE, env)
     return g.standard_normal((steps, n, 2)).astype(np.float32)
+
+
+def social_graph(n: int, seed: int = 0, k_min: int = 5, k_max: int = 2000, alpha: float = 2.5):
+    """Undirected social graph as CSR of incoming edges, both directions stored.
+
+    Degrees follow a discrete power law P(k) ~ k^-alpha on [k_min, k_max]
+    (mean about 14 for the defaults); stubs are paired at random
+    (configuration model), self loops dropped, repeated pairs kept.  Each
+    undirected pair draws one weight U[0, 1) used by both directions.  Within
+    a node's row, edges are in the order the pairing produced them.
+    Returns (row_ptr int64 [n + 1], col int32 [E], weight float32 [E]).
+    """
+    g = rng(seed, PURPOSE_GRAPH)
+    u = g.random(n)
+    a1 = 1.0 - alpha
+    k = (k_min ** a1 + u * (k_max ** a1 - k_min ** a1)) ** (1.0 / a1)
+    deg = np.floor(k).astype(np.int64)
+    stubs = np.repeat(np.arange(n, dtype=np.int64), deg)
+    g.shuffle(stubs)
+    m = stubs.shape[0] // 2
+    a, b = stubs[:m], stubs[m:2 * m]
+    keep = a != b
+    a, b = a[keep], b[keep]
+    w = g.random(a.shape[0]).astype(np.float32)
+    me = np.concatenate([a, b])
+    you = np.concatenate([b, a])
+    ww = np.concatenate([w, w])
+    order = np.argsort(me, kind="stable")
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(me, minlength=n), out=row_ptr[1:])
+    return row_ptr, you[order].astype(np.int32), ww[order]
+
+
+def opinions(n: int, seed: int = 0) -> np.ndarray:
+    """Initial opinions U[0, 1), FP32."""
+    return rng(seed, PURPOSE_GRAPH, 1).random(n).astype(np.float32)
 
 
 def poisson_arrivals(rate: float, duration: float, seed: int = 0):

@@ -9,10 +9,11 @@ in ``flock_oracle.c`` (all-pairs, double-precision sensing).  ``policy_forward``
 is the double-precision policy network in ``policy.py``; ``rl.py`` holds the
 experience-collection pieces (Gaussian action sampling, the critic, the
 truncated advantage estimator); ``graph.py`` the opinion-dynamics graph
-interaction.
+interaction.  ``oracle_move_tag`` / ``oracle_sense_tag`` are the tag
+environment (runners and chasers) of Sec. 4.2.
 
-Parity pins: every function here is pinned by ``tests/test_oracle_pins.py``
-``tests/test_oracle_rl_pins.py`` and ``tests/test_oracle_graph_pins.py``
+Parity pins: every function here is pinned by ``tests/test_oracle_pins.py``,
+``tests/test_oracle_rl_pins.py``, ``tests/test_oracle_tag_pins.py`` and ``tests/test_oracle_graph_pins.py``
 against closed forms, brute-force lattice
 counts, invariants, statistics and library densities.
 """
@@ -67,6 +68,19 @@ def _load():
                                      opt_i32, opt_i32, opt_i32, opt_i32,
                                      ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_sense.restype = None
+        lib.oracle_move_tag.argtypes = [ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, _f32p, _f32p, _f32p, _f32p, _f32p]
+        lib.oracle_move_tag.restype = None
+        lib.oracle_sense_tag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, _f32p, _f32p, _f32p,
+                                         ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_double, ctypes.c_double,
+                                         _f64p, _i32p, _i32p, _f64p,
+                                         opt_i32, opt_i32, opt_i32, opt_i32,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_sense_tag.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -137,6 +151,55 @@ def oracle_sense(x, y, th, box, radius=8.0, collide=0.5, sectors=16, r_nb=0.1, r
                              float(eps_d), float(eps_phi), obs, n_nb, n_col, reward,
                              nb_lo.ctypes.data, nb_hi.ctypes.data, col_lo.ctypes.data,
                              col_hi.ctypes.data, dstrict.ctypes.data, dloose.ctypes.data)
+    return SenseResult(obs=obs, n_nb=n_nb, n_col=n_col, reward=reward, nb_lo=nb_lo,
+                       nb_hi=nb_hi, col_lo=col_lo, col_hi=col_hi, dmin_strict=dstrict,
+                       dmin_loose=dloose, agents=lst)
+
+
+def oracle_move_tag(state, act, box, max_turn=0.2, s_max=2.0):
+    """Tag move (Sec. 4.2): turn by the clamped first action, move at speed clamp(a1, 0, s_max)."""
+    x, y, th, s = (np.array(a, dtype=np.float32, copy=True) for a in state)
+    a = np.ascontiguousarray(act, dtype=np.float32).reshape(-1)
+    n = x.shape[0]
+    assert a.shape[0] == 2 * n
+    _load().oracle_move_tag(n, float(box), float(max_turn), float(s_max), x, y, th, s, a)
+    return x, y, th, s
+
+
+def oracle_sense_tag(x, y, th, box, n_chasers, radius=8.0, touch=0.5, sectors=64, r_near=0.1,
+                     r_caught=-1.0, r_catch=1.0, agents=None, eps_d=0.0, eps_phi=0.0,
+                     fov=TWO_PI) -> SenseResult:
+    """Tag view (runner channel, then chaser channel), counts and reward, all pairs, FP64.
+
+    ``n_nb`` holds the runners within the vision range and ``n_col`` the
+    touches with agents of the other type (fields named as for the flock).
+    """
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    th = np.ascontiguousarray(th, dtype=np.float32)
+    n = x.shape[0]
+    if not 1 <= sectors <= 256:
+        raise ValueError("sectors must be in [1, 256]")
+    if agents is None:
+        n_list, lst, lst_ptr = n, None, None
+    else:
+        lst = np.ascontiguousarray(agents, dtype=np.int32)
+        n_list, lst_ptr = lst.shape[0], lst.ctypes.data
+    w = 2 * sectors
+    obs = np.zeros((n_list, w), np.float64)
+    n_nb = np.zeros(n_list, np.int32)
+    n_col = np.zeros(n_list, np.int32)
+    reward = np.zeros(n_list, np.float64)
+    nb_lo, nb_hi, col_lo, col_hi = (np.zeros(n_list, np.int32) for _ in range(4))
+    dstrict = np.zeros((n_list, w), np.float64)
+    dloose = np.zeros((n_list, w), np.float64)
+    if n_list > 0:
+        _load().oracle_sense_tag(n, int(n_chasers), float(box), float(radius), float(touch),
+                                 int(sectors), float(fov), float(r_near), float(r_caught),
+                                 float(r_catch), x, y, th, n_list, lst_ptr, float(eps_d),
+                                 float(eps_phi), obs, n_nb, n_col, reward, nb_lo.ctypes.data,
+                                 nb_hi.ctypes.data, col_lo.ctypes.data, col_hi.ctypes.data,
+                                 dstrict.ctypes.data, dloose.ctypes.data)
     return SenseResult(obs=obs, n_nb=n_nb, n_col=n_col, reward=reward, nb_lo=nb_lo,
                        nb_hi=nb_hi, col_lo=col_lo, col_hi=col_hi, dmin_strict=dstrict,
                        dmin_loose=dloose, agents=lst)

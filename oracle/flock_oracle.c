@@ -259,6 +259,153 @@ void oracle_sense(int n, double box, double radius, double collide, int v, doubl
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Tag environment (Sec. 4.2): runners and chasers.                           */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 4.2: two agent types; chasers are rewarded for touching runners,
+ * runners for staying close to other runners and penalised for touching a
+ * chaser; the view has two colour channels (runners, chasers) of v = 64
+ * sectors each (observation 128 = 2 x 64); the action turns the heading by
+ * at most theta_max and moves the agent along it at a speed in [0, s_max].
+ * Fig. 6: one agent in eleven is a chaser (a tenth of the runners' number).
+ *
+ * Readings: agents 0 .. n_chasers-1 are the chasers, the rest runners; the
+ * second action component is the speed itself (clamped to [0, s_max]), the
+ * rest of the move is the flock's; a touch is d < r_touch (strict), between
+ * agents of different types; a runner's reward is r_near per runner within
+ * the vision range plus r_caught per chaser touching it; a chaser's is
+ * r_catch per runner it touches; both channels use the flock's sector
+ * geometry and field of view.
+ */
+
+/* In place; act[i] = (turn, speed). */
+void oracle_move_tag(int n, float box, float max_turn, float s_max,
+                     float *x, float *y, float *th, float *s, const float *act)
+{
+    const float two_pi_f = (float)TWO_PI_D;
+    for (int i = 0; i < n; ++i) {
+        float turn = clamp_action(act[2 * i + 0], -max_turn, max_turn);
+        float sp = clamp_action(act[2 * i + 1], 0.0f, s_max);
+
+        float h = th[i] + turn;
+        if (h < 0.0f) h = h + two_pi_f;
+        if (h >= two_pi_f) h = h - two_pi_f;
+
+        float c = (float)cos((double)h);
+        float sn = (float)sin((double)h);
+        float nx = x[i] + sp * c;
+        if (nx < 0.0f) nx = nx + box;
+        if (nx >= box) nx = nx - box;
+        float ny = y[i] + sp * sn;
+        if (ny < 0.0f) ny = ny + box;
+        if (ny >= box) ny = ny - box;
+
+        x[i] = nx;
+        y[i] = ny;
+        th[i] = h;
+        s[i] = sp;
+    }
+}
+
+/*
+ * View (two channels), counts and reward of each agent in `list`.
+ * obs[n_list][2v]: channel 0 (runners) then channel 1 (chasers).
+ * n_near[r]: runners within the vision range (other than i);
+ * n_touch[r]: agents of the other type closer than r_touch.
+ * Bands as in oracle_sense: near/touch count ranges over pairs within
+ * eps_d of the radius, dmin_strict / dmin_loose [n_list][2v].
+ */
+void oracle_sense_tag(int n, int n_chasers, double box, double radius, double r_touch, int v,
+                      double fov, double r_near, double r_caught, double r_catch,
+                      const float *x, const float *y, const float *th,
+                      int n_list, const int *list, double eps_d, double eps_phi,
+                      double *obs, int *n_near, int *n_touch, double *reward,
+                      int *near_lo, int *near_hi, int *touch_lo, int *touch_hi,
+                      double *dmin_strict, double *dmin_loose)
+{
+    const int full = fov >= TWO_PI_D;
+    const double eps_sector = eps_phi * (double)v / (full ? TWO_PI_D : fov);
+    if (v < 1 || v > 256) return;
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int r = 0; r < n_list; ++r) {
+        const int i = list ? list[r] : r;
+        const int ti = i < n_chasers;
+        const double xi = (double)x[i], yi = (double)y[i], thi = (double)th[i];
+        double dmin[512], dstrict[512], dloose[512];
+        for (int k = 0; k < 2 * v; ++k) {
+            dmin[k] = INFINITY;
+            dstrict[k] = INFINITY;
+            dloose[k] = INFINITY;
+        }
+        int nr = 0, nt = 0, nrl = 0, nrh = 0, ntl = 0, nth = 0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const int tj = j < n_chasers;
+            double dx = min_image((double)x[j] - xi, box);
+            double dy = min_image((double)y[j] - yi, box);
+            double d = sqrt(dx * dx + dy * dy);
+            if (d >= radius + eps_d) continue;
+
+            int k = 0, seen = 1;
+            double t = 0.0;
+            if (d > 0.0) {
+                double phi = relative_bearing(dx, dy, thi);
+                t = view_position(phi, v, fov);
+                if (full) {
+                    k = sector_of(phi, v);
+                } else {
+                    seen = t >= 0.0 && t < (double)v;
+                    k = seen ? (int)floor(t) : -1;
+                }
+            } else if (!full) {
+                t = 0.5 * (double)v;
+                k = (int)floor(t);
+            }
+            const int ch = tj * v;  /* channel of j */
+            if (d < radius) {
+                if (!tj) nr += 1;
+                if (seen && d < dmin[ch + k]) dmin[ch + k] = d;
+            }
+            if (tj != ti && d < r_touch) nt += 1;
+
+            int sure_in = d < radius - eps_d;
+            if (!tj) {
+                nrl += sure_in;
+                nrh += 1;
+            }
+            if (tj != ti) {
+                ntl += d < r_touch - eps_d;
+                nth += d < r_touch + eps_d;
+            }
+            int k_lo = k, k_hi = k;
+            if (d > 0.0 && eps_sector > 0.0) {
+                k_lo = (int)floor(t - eps_sector);
+                k_hi = (int)floor(t + eps_sector);
+            }
+            if (sure_in && seen && k_lo == k_hi && d < dstrict[ch + k]) dstrict[ch + k] = d;
+            for (int kk = k_lo; kk <= k_hi; ++kk) {
+                if (!full && (kk < 0 || kk >= v)) continue;
+                int kw = ((kk % v) + v) % v;
+                if (d < dloose[ch + kw]) dloose[ch + kw] = d;
+            }
+        }
+        for (int k = 0; k < 2 * v; ++k) {
+            obs[(size_t)r * 2 * v + k] = isinf(dmin[k]) ? 0.0 : 1.0 - dmin[k] / radius;
+            if (dmin_strict) dmin_strict[(size_t)r * 2 * v + k] = dstrict[k];
+            if (dmin_loose) dmin_loose[(size_t)r * 2 * v + k] = dloose[k];
+        }
+        n_near[r] = nr;
+        n_touch[r] = nt;
+        reward[r] = ti ? r_catch * (double)nt : r_near * (double)nr + r_caught * (double)nt;
+        if (near_lo) near_lo[r] = nrl;
+        if (near_hi) near_hi[r] = nrh;
+        if (touch_lo) touch_lo[r] = ntl;
+        if (touch_hi) touch_hi[r] = nth;
+    }
+}
+
 /* Number of OpenMP threads the sense loop uses (1 without OpenMP). */
 int oracle_num_threads(void)
 {

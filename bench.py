@@ -203,6 +203,104 @@ def bench_serving(flock, workloads, duration, rate=20.0, lo=500, hi=50000, steps
             "poisson": poisson, "burst": burst_res}
 
 
+def bench_rollout(flock, workloads, reps=3):
+    """Experience collection of one training step (Sec. 5: t = 128 updates).
+
+    One env with the paper's flock settings at 16,000 agents; 128 sampled
+    closed-loop steps written into the rollout buffers (env_rollout, one HIP
+    graph), the critic over all 129 x 16,000 views, then the advantages.
+    """
+    import torch
+    pf = workloads.WORKLOADS["paper_flock10k"]
+    n, T = 16000, 128
+    p = flock.Params(n_agents=n, box=pf["box"], radius=pf["radius"], sectors=pf["sectors"],
+                     fov=math.radians(pf["fov_deg"]), flags=flock.ENV_FLAG_SPEED_OBS,
+                     cell_reach=2)
+    env = flock.Env(p)
+    env.set_state(*[torch.from_numpy(a).cuda() for a in workloads.uniform_state(n, pf["box"], seed=77)])
+    obs0 = env.reset()
+    b = flock.Batch([env])
+    d = p.obs_dim
+    aw, ab = workloads.xavier_weights([d, 64, 64, 2], seed=1)
+    cw, cb = workloads.xavier_weights([d, 64, 64, 1], seed=2)
+    pol, cri = flock.Policy(aw, ab), flock.Critic(cw, cb)
+    obs = torch.empty(T + 1, n, d, device="cuda")
+    act = torch.empty(T, n, 2, device="cuda")
+    logp = torch.empty(T, n, device="cuda")
+    rew = torch.empty(T, n, device="cuda")
+    val = torch.empty(T + 1, n, device="cuda")
+    adv = torch.empty(T, n, device="cuda")
+    ret = torch.empty(T, n, device="cuda")
+    eps = torch.from_numpy(workloads.policy_noise(T, n, seed=3)).cuda()
+    log_std = (-1.6, -2.3)
+    stream = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times = []
+    with torch.cuda.stream(stream):
+        obs[0].copy_(obs0)
+        for rep in range(reps + 1):
+            ev[0].record(stream)
+            b.rollout(pol, T, obs, act, rew, logp=logp, eps=eps, log_std=log_std, stream=stream)
+            ev[1].record(stream)
+            cri.value(obs, out=val, stream=stream)
+            ev[2].record(stream)
+            flock.gae(rew, val, 0.99, 0.95, adv=adv, ret=ret, stream=stream)
+            ev[3].record(stream)
+            obs[0].copy_(obs[T])
+            stream.synchronize()
+            if rep:   # the first pass captures the graph
+                times.append([ev[k].elapsed_time(ev[k + 1]) for k in range(3)])
+    assert torch.isfinite(adv).all() and torch.isfinite(val).all()
+    t = np.median(np.asarray(times), axis=0)
+    gae_bytes = 16 * T * n
+    return {"workload": f"one env, {n:,} agents, the paper's flock settings (box 100, vision 10, "
+                        f"128 sectors, 250 degrees, speed in the view), {T} sampled steps per "
+                        "collection; critic over the 129 x N views; advantages",
+            "rollout_ms": float(t[0]), "critic_ms": float(t[1]), "gae_ms": float(t[2]),
+            "collect_ms": float(t.sum()), "agent_steps_per_s": n * T / (t[0] * 1e-3),
+            "buffer_bytes": int((obs.numel() + act.numel() + logp.numel() + rew.numel()
+                                 + val.numel() + adv.numel() + ret.numel()) * 4),
+            "gae_hbm": {"bytes_per_launch": gae_bytes,
+                        "achieved_GBps": gae_bytes / (t[2] * 1e-3) / 1e9,
+                        "frac": gae_bytes / (t[2] * 1e-3) / HBM_PEAK}}
+
+
+def bench_graph(flock, workloads, steps=50):
+    """Opinion dynamics over a 1,000,000-node power-law social graph (Sec. 2.1)."""
+    import torch
+    n = 1_000_000
+    rp, col, w = workloads.social_graph(n, seed=0)
+    E = int(rp[-1])
+    rp_d = torch.from_numpy(rp).cuda()
+    col_d = torch.from_numpy(col).cuda()
+    w_d = torch.from_numpy(w).cuda()
+    a = torch.from_numpy(workloads.opinions(n, seed=0)).cuda()
+    b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    res = {}
+    for lanes in (1, 4, 16):
+        for _ in range(3):
+            flock.opinion_step(rp_d, col_d, w_d, a, b, 0.3, 0.5, lanes=lanes)
+            a, b = b, a
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            flock.opinion_step(rp_d, col_d, w_d, a, b, 0.3, 0.5, lanes=lanes)
+            a, b = b, a
+        ev[1].record()
+        ev[1].synchronize()
+        res[lanes] = ev[0].elapsed_time(ev[1]) / steps
+    best = min(res, key=res.get)
+    ms = res[best]
+    algo = 16 * n + 12 * E
+    return {"workload": f"{n:,} nodes, {E:,} directed edges (power-law degrees 5..2,000), "
+                        "threshold 0.3, strength 0.5",
+            "ms_per_step_by_lanes": {str(k): v for k, v in res.items()}, "lanes": best,
+            "ms_per_step": ms, "edges_per_s": E / (ms * 1e-3),
+            "hbm": {"algorithmic_bytes_per_step": algo, "achieved_GBps": algo / (ms * 1e-3) / 1e9,
+                    "frac": algo / (ms * 1e-3) / HBM_PEAK}}
+
+
 def cpu_baseline(seconds):
     """The oracle (all-pairs, FP64 view) on the host, 5,000-agent env, bounded sample."""
     import oracle
@@ -291,7 +389,10 @@ def main():
     ap.add_argument("--envs", type=int, default=200, help="5,000-agent envs in the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only-main", action="store_true", help="skip the 50k and plain legs")
+    ap.add_argument("--only-main", action="store_true", help="run the main batched leg only")
+    ap.add_argument("--legs", default="plain,50k,uneven,paper,rollout,graph,serving",
+                    help="comma list of extra legs: plain, 50k, uneven, paper, rollout, graph, "
+                         "serving")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
@@ -324,10 +425,12 @@ def main():
     del batch
     main_work = sweep_work(envs)
     extra = {}
-    if not args.only_main:
+    legs = set() if args.only_main else {x for x in args.legs.split(",") if x}
+    if "plain" in legs:
         log("[bench] plain 5k")
         extra["plain"] = bench_plain(envs[0], 5000, K, W, seed=2)
-        del envs
+    del envs
+    if "50k" in legs:
         for name, init in (("blobs50k", "blobs"), ("uniform50k", "uniform")):
             log(f"[bench] {name} plain")
             e50 = make_envs(flock, workloads, 50000, 1000.0, 20, init, 2000)
@@ -340,6 +443,7 @@ def main():
             extra[name] = {"plain": plain, "batched_x20": {**bat, "sweep_lanes": b50.sweep_lanes,
                                                            "lanes_ms": lane_ms}}
             del b50, e50
+    if "uneven" in legs:
         log("[bench] uneven 256 envs")
         ns, boxes = workloads.uneven_env_sizes(256, 100, 20000, seed=0)
         states = [workloads.uniform_state(int(n), float(b), seed=0, env=k)
@@ -359,6 +463,7 @@ def main():
                               "tuned_ms": tune_ms,
                               **bench_batched(flock, bu, K, W, seed=5, timed_reps=10)}
         del bu, envs_u
+    if "paper" in legs:
         log("[bench] paper flock 10k")
         pf = workloads.WORKLOADS["paper_flock10k"]
         pf_params = dict(sectors=pf["sectors"], radius=pf["radius"],
@@ -383,10 +488,15 @@ def main():
             "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"]),
             "sweep_hbm_frac": pf_bytes * b10.n / (bat["phase_ms"]["sweep"] * 1e-3) / HBM_PEAK}
         del b10, e10
+    if "rollout" in legs:
+        log("[bench] experience collection")
+        extra["rollout"] = bench_rollout(flock, workloads)
+    if "graph" in legs:
+        log("[bench] graph interaction")
+        extra["graph"] = bench_graph(flock, workloads)
+    if "serving" in legs:
         log("[bench] serving")
         extra["serving"] = bench_serving(flock, workloads, args.serve_seconds)
-    else:
-        del envs
 
     if args.copy_calib_mib:
         src = torch.ones(args.copy_calib_mib << 18, device="cuda")

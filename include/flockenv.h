@@ -35,10 +35,11 @@
  *
  * State layout (structure of arrays, FP32, agent order): x[n], y[n] in
  * [0, box), heading th[n] in [0, 2pi), speed s[n] in [s_min, s_max].
- * Actions act[n][2]: column 0 = turn (rad), column 1 = speed change.
- * View obs[n][d] (agent-major), d = v, or v + 1 with ENV_FLAG_SPEED_OBS:
- * 1 - d_min/radius per sector, 0 when empty, then the agent's speed.
- * Reward reward[n] = r_nb * n_neighbours + r_col * n_collisions.
+ * Actions act[n][2]: column 0 = turn (rad), column 1 = speed change (the
+ * speed itself for tag envs).  View obs[n][d] (agent-major): d = v (2v for
+ * tag envs), + 1 with ENV_FLAG_SPEED_OBS; 1 - d_min/radius per sector, 0
+ * when empty, then the agent's speed.  Reward reward[n] = r_nb *
+ * n_neighbours + r_col * n_collisions (tag envs: see env_params_t).
  */
 #ifndef FLOCKENV_H
 #define FLOCKENV_H
@@ -67,6 +68,7 @@ enum {
 /* flags */
 #define ENV_FLAG_COUNTS 1    /* keep per-agent neighbour / collision counts   */
 #define ENV_FLAG_SPEED_OBS 2 /* append the agent's speed to its view row      */
+#define ENV_FLAG_TAG 4       /* tag environment: runners and chasers          */
 
 /*
  * Environment parameters (Sec. 4.1).  Requirements, else ENV_EINVAL:
@@ -83,6 +85,15 @@ enum {
  * heading from its right edge, counter-clockwise.  Agents outside the arc
  * are not seen but still count in the reward (Eq. (1)).  A coincident
  * agent is taken to lie on the heading.
+ *
+ * Tag (ENV_FLAG_TAG, Sec. 4.2): agents 0 .. n_chasers-1 are chasers, the
+ * rest runners (0 <= n_chasers <= n_agents).  The second action component
+ * is the speed itself, clamped to [0, s_max] (max_dspeed and s_min are not
+ * used).  The view has two channels of v sectors, runners then chasers
+ * (row length 2v, + 1 with ENV_FLAG_SPEED_OBS).  A touch is a pair of
+ * different types closer than `collide`.  Counts: n_nb = runners within
+ * `radius`, n_col = touches.  Reward: runner r_nb n_nb + r_col n_col,
+ * chaser r_catch n_col.  Tag and flock envs do not mix in a batch.
  */
 typedef struct env_params {
     int32_t n_agents;
@@ -99,6 +110,8 @@ typedef struct env_params {
     int32_t cell_reach;
     int32_t flags;     /* ENV_FLAG_*                                     */
     float fov;         /* field of view (radians), 0 = full              */
+    int32_t n_chasers; /* tag: agents 0 .. n_chasers-1 are chasers       */
+    float r_catch;     /* tag: chaser reward per runner it touches       */
 } env_params_t;
 
 typedef struct flock_env env_t;
@@ -234,12 +247,97 @@ void pol_destroy(pol_t *pol);
 /* act[n][2] = policy(obs[n][in]) (device), BF16 MFMA, FP32 accumulate. */
 int pol_forward(pol_t *pol, const float *obs, int64_t n, float *act, void *stream);
 
+/* Critic network of Sec. 5 (two hidden layers of 64, tanh): in -> hidden ->
+ * hidden -> 1, linear output.  w_host: W1[in][hidden], b1[hidden],
+ * W2[hidden][hidden], b2[hidden], W3[hidden][1], b3[1]; same precision and
+ * workspace size (pol_workspace_bytes) as the actor.  The handle works only
+ * with pol_value; pol_destroy releases it. */
+int pol_create_value(const float *w_host, int in_dim, int hidden, void *ws, size_t bytes,
+                     void *stream, pol_t **out);
+
+/* value[n] = critic(obs[n][in]) (device FP32).  ENV_EINVAL for an actor. */
+int pol_value(pol_t *critic, const float *obs, int64_t n, float *value, void *stream);
+
+/* PPO's Gaussian action sampling round the actor's mean (Sec. 4.3, Fig. 5):
+ * act[i] = mean_i + exp(log_std) * eps[i] (eps: device [n][2] standard
+ * normal draws, supplied by the caller), and, when logp is not NULL,
+ * logp[i] = -(eps_i0^2 + eps_i1^2)/2 - log_std_0 - log_std_1 - log(2 pi),
+ * the log density of the sample.  log_std: host float[2].  The environment
+ * clamps the sampled action to its range when it applies it. */
+int pol_sample(pol_t *pol, const float *obs, int64_t n, const float *log_std, const float *eps,
+               float *act, float *logp, void *stream);
+
+/* Experience collection (Sec. 4.3, Fig. 5; Sec. 5: t = 128 updates per
+ * training step): `steps` closed-loop batched steps whose views, actions,
+ * log densities and rewards are written straight into the caller's rollout
+ * buffers (device, rows in batch order, G = off[n_envs], d as for env_step):
+ *   obs    [steps + 1][G][d]  block 0 holds the current view on entry
+ *                             (from env_reset or the last step); block
+ *                             k + 1 receives the view after step k
+ *   act    [steps][G][2]      actions taken (sampled, before the clamp)
+ *   logp   [steps][G]         log density of each sample (NULL: not kept)
+ *   reward [steps][G]
+ * eps (device [steps][G][2] standard normals) and log_std (host float[2])
+ * select Gaussian sampling as pol_sample; eps = NULL takes the mean action
+ * (then logp must be NULL).  FP64 returns accumulate as for env_step.  The
+ * launches of all steps are captured once into a HIP graph and replayed
+ * (re-captured when an argument changes); `stream` must not be the null
+ * stream.  Results equal `steps` rounds of pol_sample (or pol_forward) and
+ * env_step_batched. */
+int env_rollout(env_batch_t *b, pol_t *pol, int steps, const float *log_std, const float *eps,
+                float *obs, float *act, float *logp, float *reward, void *stream);
+
+/* Tag rollout (Sec. 4.2, 4.3: runners and chasers train independent
+ * policies): as env_rollout, with each row's action from the policy of its
+ * agent's type.  log_std: host float[4], the runner's two values then the
+ * chaser's.  ENV_EINVAL unless the batch holds tag envs. */
+int env_rollout_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, int steps,
+                    const float *log_std, const float *eps, float *obs, float *act, float *logp,
+                    float *reward, void *stream);
+
+/* Tag closed-loop step: act = runner or chaser policy (mean action) of each
+ * row's obs by its type, then one batched step, as env_step_policy. */
+int env_step_policy_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, float *act, float *obs,
+                        float *reward, void *stream);
+
+/* PPO's truncated advantage estimator over a rollout (Sec. 4.3, Sec. 5), per
+ * agent: delta_t = r_t + gamma V_{t+1} - V_t, A_t = delta_t + gamma lambda
+ * A_{t+1} with A_steps = 0, and value targets R_t = A_t + V_t.
+ * reward [steps][n], value [steps + 1][n] (row `steps` is the bootstrap
+ * value of the state after the last step), adv and ret [steps][n]; device
+ * FP32, evaluated in FP64 and rounded once.  gamma, lambda in [0, 1]. */
+int rl_gae(int steps, int64_t n, float gamma, float lambda, const float *reward,
+           const float *value, float *adv, float *ret, void *stream);
+
 /* Closed-loop batched step: act = policy(obs) for every agent, then one
  * batched step with those actions.  obs (device [G][d]) is read as the
  * current view and overwritten by the new one; act (device [G][2]) receives
  * the actions taken; reward (device [G]). */
 int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
                     void *stream);
+
+/* ---------------------------------------------------- graph interaction */
+
+/* One step of the opinion-dynamics model of Sec. 2.1 (the engine's
+ * interaction over graph edges): for every node i and each incoming edge e
+ * = (i, j) in CSR order, when |op_in[i] - op_in[j]| < threshold (FP32),
+ * new_i <- (1 - strength w_e) new_i + strength w_e op_in[j], starting from
+ * new_i = op_in[i]; then op_out[i] = new_i (the self interaction).  Every
+ * test reads the step's input opinions.
+ *   row_ptr  device int64 [n + 1]: edges of node i are row_ptr[i] ..
+ *            row_ptr[i + 1] - 1 (ranges are clamped to [0, n_edges])
+ *   col      device int32 [n_edges]: j of each edge (j outside [0, n) is
+ *            skipped)
+ *   weight   device FP32 [n_edges]
+ *   op_in, op_out  device FP32 [n], distinct
+ * Updates run in FP64, rounded once to FP32.  lanes: lanes per node (1, 4,
+ * 16, 64; 0 = from the mean degree).  With lanes = 1 each node applies its
+ * edges one by one in the stated order; with more, chunks of the row are
+ * composed as affine maps (the same map up to FP64 rounding).  0 <= n <
+ * 2^31.  ENV_EINVAL on bad sizes, NULL arrays, op_in == op_out. */
+int gr_opinion_step(int64_t n, int64_t n_edges, const int64_t *row_ptr, const int32_t *col,
+                    const float *weight, float threshold, float strength, const float *op_in,
+                    float *op_out, int lanes, void *stream);
 
 /* -------------------------------------------------------------- serving */
 

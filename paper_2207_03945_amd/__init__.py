@@ -6,6 +6,6 @@ HIP kernels of ``libflockenv.so`` behind the C ABI of ``include/flockenv.h``.
 ``flockenv`` is its ctypes binding.
 """
 from .flockenv import (  # noqa: F401
-    ENV_FLAG_COUNTS, ENV_FLAG_SPEED_OBS, Batch, Env, FlockError, Params, Policy, Server, lib,
-    request_bytes, workspace_bytes,
+    ENV_FLAG_COUNTS, ENV_FLAG_SPEED_OBS, ENV_FLAG_TAG, Batch, Critic, Env, FlockError, Params, Policy, Server,
+    gae, lib, opinion_step, request_bytes, workspace_bytes,
 )

@@ -63,8 +63,14 @@ int check_params(const env_params_t *p) {
     if (!finite(p->s_min) || !finite(p->s_max) || p->s_min < 0.0f || p->s_min > p->s_max)
         return fail(ENV_EINVAL, "need 0 <= s_min <= s_max");
     if (p->cell_reach < 0 || p->cell_reach > 2) return fail(ENV_EINVAL, "cell_reach must be 0, 1 or 2");
-    if (p->flags & ~(ENV_FLAG_COUNTS | ENV_FLAG_SPEED_OBS))
+    if (p->flags & ~(ENV_FLAG_COUNTS | ENV_FLAG_SPEED_OBS | ENV_FLAG_TAG))
         return fail(ENV_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ENV_FLAG_TAG) {
+        if (p->n_chasers < 0 || p->n_chasers > p->n_agents)
+            return fail(ENV_EINVAL, "n_chasers must be in [0, n_agents]");
+        if (!finite(p->r_catch)) return fail(ENV_EINVAL, "r_catch must be finite");
+        if (p->sectors > 128) return fail(ENV_EINVAL, "tag envs take at most 128 sectors per channel");
+    }
     if (!finite(p->fov) || p->fov < 0.0f || p->fov > kTwoPiF)
         return fail(ENV_EINVAL, "fov must be 0 (full view) or in (0, 2 pi]");
     return ENV_OK;
@@ -122,6 +128,9 @@ DevEnv make_desc(const env_params_t &p, const Geometry &gm) {
     d.max_dspeed = p.max_dspeed;
     d.s_min = p.s_min;
     d.s_max = p.s_max;
+    d.tag = (p.flags & ENV_FLAG_TAG) ? 1 : 0;
+    d.n_chasers = d.tag ? p.n_chasers : 0;
+    d.r_catch = p.r_catch;
     if (full_view(p)) {
         d.fov_half = 0.0f;
         d.fov_t = 1.0f;
@@ -169,7 +178,8 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool flock::full_view(const env_params_t &p) { return p.fov == 0.0f || p.fov >= kTwoPiF; }
 int flock::obs_dim_of(const env_params_t &p) {
-    return p.sectors + ((p.flags & ENV_FLAG_SPEED_OBS) ? 1 : 0);
+    const int channels = (p.flags & ENV_FLAG_TAG) ? 2 : 1;
+    return channels * p.sectors + ((p.flags & ENV_FLAG_SPEED_OBS) ? 1 : 0);
 }
 
 int flock::set_error(int code, const char *fmt, ...) {
@@ -227,13 +237,11 @@ int upload_own(env_t *e, hipStream_t s) {
 
 }  // namespace
 
+// An instantiated graph and the launch arguments it was captured with.
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    int k = 0;
-    const float *act = nullptr;
-    float *obs = nullptr, *reward = nullptr;
-    hipStream_t stream = nullptr;
+    std::vector<uint64_t> key;
 };
 
 struct flock_batch {
@@ -244,7 +252,8 @@ struct flock_batch {
     std::vector<int64_t> off;
     StepPlan plan;
     bool uploaded = false;
-    GraphCache gc[2];                // graphs by starting table
+    GraphCache gc[2];                // K-step graphs by starting table
+    GraphCache rgc[2];               // rollout graphs by starting table
     hipEvent_t events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -316,6 +325,46 @@ size_t sort_scratch_bytes(int64_t G, int64_t C, int E) {
 
 }  // namespace flock
 
+static void drop_graph(GraphCache &gc) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+    gc = GraphCache{};
+}
+
+static void drop_graphs(env_batch_t *b) {
+    for (auto &gc : b->gc) drop_graph(gc);
+    for (auto &gc : b->rgc) drop_graph(gc);
+}
+
+// Capture what `enqueue` launches on `s` into `gc`, unless gc already holds a
+// graph captured with the same key.
+template <typename F>
+static int capture_graph(GraphCache &gc, std::vector<uint64_t> key, hipStream_t s, F enqueue) {
+    if (gc.exec && gc.key == key) return ENV_OK;
+    drop_graph(gc);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const hipError_t le = enqueue();
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : e, "graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    gc.exec = exec;
+    gc.graph = graph;
+    gc.key = std::move(key);
+    return ENV_OK;
+}
+
+static uint64_t key_of(const void *p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); }
+
 extern "C" {
 
 const char *env_last_error(void) { return g_err.c_str(); }
@@ -354,6 +403,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.v = p->sectors;
     e->plan.obs_dim = obs_dim_of(*p);
     e->plan.fov = full_view(*p) ? 0 : 1;
+    e->plan.tag = (p->flags & ENV_FLAG_TAG) ? 1 : 0;
     e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors);
     e->plan.scan_blocks = scan_blocks_for(e->plan.C);
     *out = e;
@@ -464,6 +514,8 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *ba
         if (e->p.sectors != envs[0]->p.sectors)
             return fail(ENV_EINVAL, "env %d has %d sectors, env 0 has %d", k, e->p.sectors,
                         envs[0]->p.sectors);
+        if ((e->p.flags & ENV_FLAG_TAG) != (envs[0]->p.flags & ENV_FLAG_TAG))
+            return fail(ENV_EINVAL, "env %d and env 0 differ in ENV_FLAG_TAG", k);
         if (obs_dim_of(e->p) != obs_dim_of(envs[0]->p))
             return fail(ENV_EINVAL, "env %d and env 0 differ in ENV_FLAG_SPEED_OBS", k);
         if (fov && !full_view(e->p)) *fov = 1;
@@ -533,19 +585,14 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.v = v;
     b->plan.obs_dim = obs_dim;
     b->plan.fov = fov;
+    b->plan.tag = (envs[0]->p.flags & ENV_FLAG_TAG) ? 1 : 0;
     b->plan.lanes = batch_auto_lanes(b->envs);
     b->plan.scan_blocks = scan_blocks_for(C);
     *out = b;
     return ENV_OK;
 }
 
-static void drop_graphs(env_batch_t *b) {
-    for (auto &gc : b->gc) {
-        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
-        if (gc.graph) (void)hipGraphDestroy(gc.graph);
-        gc = GraphCache{};
-    }
-}
+
 
 void env_batch_destroy(env_batch_t *b) {
     if (!b) return;
@@ -676,40 +723,16 @@ static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *o
     int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
     *table = t;
-    GraphCache &gc = b->gc[t];
-    if (gc.exec && gc.k == k_steps && gc.act == act && gc.obs == obs && gc.reward == reward &&
-        gc.stream == s)
-        return ENV_OK;
-    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
-    if (gc.graph) (void)hipGraphDestroy(gc.graph);
-    gc = GraphCache{};
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     const int64_t G = b->plan.G;
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < k_steps && le == hipSuccess; ++k)
-        le = launch_step(b->plan, t ^ (k & 1), 1, act + (size_t)k * G * 2, obs,
-                         reward + (size_t)k * G, 1, s);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(s, &graph);
-    if (le != hipSuccess || e != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(le != hipSuccess ? le : e, "graph capture");
-    }
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(e, "hipGraphInstantiate");
-    }
-    gc.exec = exec;
-    gc.graph = graph;
-    gc.k = k_steps;
-    gc.act = act;
-    gc.obs = obs;
-    gc.reward = reward;
-    gc.stream = s;
-    return ENV_OK;
+    std::vector<uint64_t> key = {(uint64_t)k_steps, key_of(act), key_of(obs), key_of(reward),
+                                 key_of(s)};
+    return capture_graph(b->gc[t], std::move(key), s, [&]() {
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < k_steps && le == hipSuccess; ++k)
+            le = launch_step(b->plan, t ^ (k & 1), 1, act + (size_t)k * G * 2, obs,
+                             reward + (size_t)k * G, 1, s);
+        return le;
+    });
 }
 
 int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs, float *reward,
@@ -729,10 +752,122 @@ int env_batch_run(env_batch_t *b, int k_steps, const float *act, float *obs, flo
     return ENV_OK;
 }
 
+}  // extern "C"
+
+// Shared by env_rollout (one policy) and env_rollout_tag (runner and chaser
+// policies; log_std then holds the runner's two values, then the chaser's).
+static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, const float *log_std,
+                        const float *eps, float *obs, float *act, float *logp, float *reward,
+                        void *stream) {
+    if (!b || !pol) return fail(ENV_EINVAL, "batch or policy is NULL");
+    const bool tag = b->plan.tag != 0;
+    if (tag != (chaser != nullptr))
+        return fail(ENV_EINVAL, tag ? "tag batches need env_rollout_tag (two policies)"
+                                    : "env_rollout_tag needs a batch of tag envs");
+    for (pol_t *q : {pol, chaser}) {
+        if (!q) continue;
+        if (policy_is_critic(q)) return fail(ENV_EINVAL, "rollouts need actors, not critics");
+        if (policy_in_dim(q) != b->plan.obs_dim)
+            return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(q),
+                        b->plan.obs_dim);
+    }
+    if (steps < 1) return fail(ENV_EINVAL, "steps must be >= 1");
+    if (!stream) return fail(ENV_EINVAL, "rollouts need a non-null stream (graph capture)");
+    if (eps && !log_std) return fail(ENV_EINVAL, "sampling (eps) needs log_std");
+    if (!eps && logp) return fail(ENV_EINVAL, "logp needs sampling (eps)");
+    const int n_ls = tag ? 4 : 2;
+    float ls[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < n_ls && log_std; ++k) {
+        if (!isfinite(log_std[k])) return fail(ENV_EINVAL, "log_std must be finite");
+        ls[k] = log_std[k];
+    }
+    const int64_t G = b->plan.G;
+    if (G > 0 && (!obs || !act || !reward)) return fail(ENV_EINVAL, "obs/act/reward is NULL");
+    hipStream_t s = as_stream(stream);
+    int t;
+    int rc = batch_prepare(b, s, &t);
+    if (rc != ENV_OK) return rc;
+    const int d = b->plan.obs_dim;
+    uint32_t lsb[4];
+    memcpy(lsb, ls, sizeof(lsb));
+    std::vector<uint64_t> key = {(uint64_t)steps, key_of(policy_weights(pol)),
+                                 key_of(chaser ? policy_weights(chaser) : nullptr), key_of(eps),
+                                 key_of(obs), key_of(act), key_of(logp), key_of(reward),
+                                 key_of(s), ((uint64_t)lsb[0] << 32) | lsb[1],
+                                 ((uint64_t)lsb[2] << 32) | lsb[3]};
+    rc = capture_graph(b->rgc[t], std::move(key), s, [&]() {
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < steps && le == hipSuccess; ++k) {
+            const int tk = t ^ (k & 1);
+            const float *o_k = obs + (size_t)k * G * d;
+            float *a_k = act + (size_t)k * G * 2;
+            const float *e_k = eps ? eps + (size_t)k * G * 2 : nullptr;
+            float *l_k = logp ? logp + (size_t)k * G : nullptr;
+            if (tag) {
+                le = policy_launch_typed(pol, b->plan, tk, 0, o_k, e_k, ls, a_k, l_k, s);
+                if (le == hipSuccess)
+                    le = policy_launch_typed(chaser, b->plan, tk, 1, o_k, e_k, ls + 2, a_k, l_k, s);
+            } else {
+                le = eps ? policy_launch_sample(pol, o_k, G, e_k, ls, a_k, l_k, s)
+                         : policy_launch(pol, o_k, G, a_k, s);
+            }
+            if (le == hipSuccess)
+                le = launch_step(b->plan, tk, 1, a_k, obs + (size_t)(k + 1) * G * d,
+                                 reward + (size_t)k * G, 1, s);
+        }
+        return le;
+    });
+    if (rc != ENV_OK) return rc;
+    hipError_t e = hipGraphLaunch(b->rgc[t].exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    batch_advance(b, steps);
+    return ENV_OK;
+}
+
+extern "C" {
+
+int env_rollout(env_batch_t *b, pol_t *pol, int steps, const float *log_std, const float *eps,
+                float *obs, float *act, float *logp, float *reward, void *stream) {
+    return rollout_impl(b, pol, nullptr, steps, log_std, eps, obs, act, logp, reward, stream);
+}
+
+int env_rollout_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, int steps,
+                    const float *log_std, const float *eps, float *obs, float *act, float *logp,
+                    float *reward, void *stream) {
+    if (!chaser) return fail(ENV_EINVAL, "chaser policy is NULL");
+    return rollout_impl(b, runner, chaser, steps, log_std, eps, obs, act, logp, reward, stream);
+}
+
+int env_step_policy_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, float *act, float *obs,
+                        float *reward, void *stream) {
+    if (!b || !runner || !chaser) return fail(ENV_EINVAL, "batch or policy is NULL");
+    if (!b->plan.tag) return fail(ENV_EINVAL, "env_step_policy_tag needs a batch of tag envs");
+    if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    for (pol_t *q : {runner, chaser}) {
+        if (policy_is_critic(q)) return fail(ENV_EINVAL, "env_step_policy_tag needs actors");
+        if (policy_in_dim(q) != b->plan.obs_dim)
+            return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(q),
+                        b->plan.obs_dim);
+    }
+    hipStream_t s = as_stream(stream);
+    int t;
+    int rc = batch_prepare(b, s, &t);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = policy_launch_typed(runner, b->plan, t, 0, obs, nullptr, nullptr, act, nullptr, s);
+    if (e == hipSuccess)
+        e = policy_launch_typed(chaser, b->plan, t, 1, obs, nullptr, nullptr, act, nullptr, s);
+    if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "env_step_policy_tag");
+    batch_advance(b, 1);
+    return ENV_OK;
+}
+
 int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
                     void *stream) {
     if (!b || !pol) return fail(ENV_EINVAL, "batch or policy is NULL");
     if (b->plan.G > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    if (policy_is_critic(pol)) return fail(ENV_EINVAL, "env_step_policy needs an actor, not a critic");
+    if (b->plan.tag) return fail(ENV_EINVAL, "tag batches need env_step_policy_tag (two policies)");
     if (policy_in_dim(pol) != b->plan.obs_dim)
         return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(pol),
                     b->plan.obs_dim);

@@ -48,6 +48,9 @@ struct DevEnv {
     // position is (bearing + fov_half) mod 1, seen iff < fov_t, sector =
     // position * sec_scale.  Full view: fov_half 0, fov_t 1, sec_scale v.
     float fov_half, fov_t, sec_scale;
+    int32_t tag;                 // tag environment (runners and chasers)
+    int32_t n_chasers;           // tag: agents 0 .. n_chasers-1 are chasers
+    float r_catch;               // tag: chaser reward per runner touched
 };
 static_assert(sizeof(DevEnv) <= 192, "DevEnv grew");
 
@@ -57,6 +60,7 @@ struct SortArrays {
     int32_t *slot;     // [G] rank of record p within its new cell
     float4 *tmp;       // [G] moved record p (old order)
     float2 *sxy;       // [G] positions in the new cell order (candidates)
+    uint8_t *stype;    // [G] tag: 1 for a chaser, in the new cell order
     int32_t *count;    // [C] agents per cell; zero between steps
     int32_t *start;    // [C + 1] exclusive prefix of count
     int32_t *part;     // [scan partials]
@@ -75,6 +79,7 @@ struct StepPlan {
     int obs_dim;  // view row length: v, or v + 1 with the speed appended
     int fov;      // any env of the plan has a limited view
     int lanes;    // lanes per agent in the sweep: 1, 4, 16 or 64
+    int tag;      // the plan's envs are tag envs (two view channels)
     int scan_blocks;  // 0 -> single-block scan
 };
 
@@ -152,6 +157,20 @@ hipError_t policy_launch(const pol_t *pol, const float *obs, int64_t n, float *a
 // env's own rows (DevEnv::obs / DevEnv::act) of descriptor table `table`.
 hipError_t policy_launch_envs(const pol_t *pol, const StepPlan &plan, int table, hipStream_t s);
 int policy_in_dim(const pol_t *pol);
+int policy_is_critic(const pol_t *pol);
+// Device address of the policy's weights (identifies what a captured graph reads).
+const void *policy_weights(const pol_t *pol);
+// act = mean + exp(log_std) * eps (eps [n][2]), logp [n] (may be null).
+hipError_t policy_launch_sample(const pol_t *pol, const float *obs, int64_t n, const float *eps,
+                                const float log_std[2], float *act, float *logp, hipStream_t s);
+// Tag: rows of one type (1 chasers, 0 runners) of a batch plan; mean
+// action when eps is null, else sampled as policy_launch_sample.
+hipError_t policy_launch_typed(const pol_t *pol, const StepPlan &plan, int table, int type,
+                               const float *obs, const float *eps, const float *log_std,
+                               float *act, float *logp, hipStream_t s);
+// value [n] = critic(obs).
+hipError_t policy_launch_value(const pol_t *pol, const float *obs, int64_t n, float *value,
+                               hipStream_t s);
 
 // Error channel shared by every C entry point (flock_api.cpp): records a
 // thread-local message for env_last_error() and returns `code`.

@@ -106,11 +106,15 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
             const float2 av =
                 act ? act[E.agent_base + id] : reinterpret_cast<const float2 *>(E.act)[id];
             const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
-            const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
             h = h + turn;
             if (h < 0.0f) h = h + kTwoPiF;
             if (h >= kTwoPiF) h = h - kTwoPiF;
-            sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+            if (E.tag) {
+                sp = fminf(fmaxf(av.y, 0.0f), E.s_max);  // tag: the action is the speed
+            } else {
+                const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
+                sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+            }
             double sd, cd;
             sincos((double)h, &sd, &cd);
             const float c = (float)cd, sn = (float)sd;
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ co
 // ------------------------------------------------------------------ scatter
 
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *__restrict__ envs,
-                                                    int n_envs, int G) {
+                                                    int n_envs, int G, int tag) {
     __shared__ int s_env;
     const int p0 = blockIdx.x * kBlock;
     if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
@@ -351,10 +355,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *
     const int pos = a.start[a.key[p]] + a.slot[p];
     const int j = pos - E.agent_base;
     const float4 r = a.tmp[p];
+    const int id = E.id_cur[i];
     E.rec_nxt[j] = r;
-    E.id_nxt[j] = E.id_cur[i];
+    E.id_nxt[j] = id;
     E.ret_nxt[j] = E.ret_cur[i];
     a.sxy[pos] = make_float2(r.x, r.y);
+    if (tag) a.stype[pos] = id < E.n_chasers ? 1 : 0;
 }
 
 // -------------------------------------------------------------------- sweep
@@ -437,8 +443,13 @@ struct ViewK {
 // centre (x or x - L) per axis; minimg selects the per-candidate minimum
 // image (single-cell envs).  kFov selects the limited-view sector
 // (candidates outside the arc are counted but update no sector).
-template <int S, int G, int UNROLL, bool kFov>
+//
+// kTag (tag environment): candidate q's type stype[q] picks the view channel
+// (minima at smin_own[(tj v + k) S]); nb counts runners in range and col
+// touches with the other type (the lane's own type is ti).
+template <int S, int G, int UNROLL, bool kFov, bool kTag>
 __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
+                                          const uint8_t *__restrict__ stype, int ti,
                                           int q, int q1, int li, int self, float offx, float xi,
                                           float offy, float yi, bool minimg, float L, float r2,
                                           float c2, const ViewK &K, int &nb, int &col) {
@@ -453,14 +464,22 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
         }
         const float d2 = __builtin_fmaf(dx, dx, dy * dy);
         const bool nbr = d2 < r2 && qq != self;
-        nb += nbr ? 1 : 0;
-        col += (nbr && d2 < c2) ? 1 : 0;
+        int ch = 0;  // view channel offset (sectors)
+        if constexpr (kTag) {
+            const int tj = stype[qq];
+            nb += (nbr && tj == 0) ? 1 : 0;
+            col += (nbr && tj != ti && d2 < c2) ? 1 : 0;
+            ch = tj * K.v;
+        } else {
+            nb += nbr ? 1 : 0;
+            col += (nbr && d2 < c2) ? 1 : 0;
+        }
         if (kFov) {
             const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
-            if (nbr && k >= 0) atomicMin(&smin_own[k * S], __float_as_uint(d2));
+            if (nbr && k >= 0) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
         } else {
             const int k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
-            if (nbr) atomicMin(&smin_own[k * S], __float_as_uint(d2));
+            if (nbr) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
         }
     };
     q += li;
@@ -484,20 +503,21 @@ constexpr int kUnroll = 4;
 // among a lane group, which keeps the lanes busy and the LDS per agent small.
 // kFov: some env of the launch has a limited field of view.  obs rows hold
 // obs_dim floats: the v sectors, then the speed when obs_dim > v.
-template <int NT, int G, bool kFov>
+template <int NT, int G, bool kFov, bool kTag>
 __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
                                               int n_envs, int Gtot, int v, int obs_dim,
                                               float *__restrict__ obs, float *__restrict__ reward,
                                               int add_ret) {
     constexpr int A = NT / G;
-    extern __shared__ uint32_t s_min[];  // [v][A]
+    extern __shared__ uint32_t s_min[];  // [channels * v][A]
+    const int vs = kTag ? 2 * v : v;     // minima per agent
     __shared__ int s_env;
     const int tid = threadIdx.x, slot = tid / G, li = tid % G;
     const int p0 = blockIdx.x * A;
     if (tid == 0) s_env = env_search(a.base, n_envs, p0);
     uint32_t *smin = s_min + slot;
     if constexpr (G > 1)
-        for (int k = li; k < v; k += G) smin[k * A] = kInfBits;
+        for (int k = li; k < vs; k += G) smin[k * A] = kInfBits;
     __syncthreads();
     const int pos = p0 + slot;
     if constexpr (G == 1) {
@@ -511,20 +531,21 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     const DevEnv &E = envs[e];
     const int j = pos - E.agent_base;
     float4 me = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    int nb = 0, col = 0;
+    int nb = 0, col = 0, ti = 0;
     if (active) {
         me = E.rec_nxt[j];
         double sd, cd;
         sincos((double)me.z, &sd, &cd);
         const float c = (float)cd, s = (float)sd;
         if constexpr (G == 1)
-            for (int k = 0; k < v; ++k) smin[k * A] = kInfBits;
+            for (int k = 0; k < vs; ++k) smin[k * A] = kInfBits;
 
         const ViewK K{c, s, E.fov_half, E.fov_t, E.sec_scale, (float)v, v};
+        ti = kTag ? (E.id_nxt[j] < E.n_chasers ? 1 : 0) : 0;
         const float L = E.box, r2 = E.r2, c2 = E.c2;
         const int ncell = E.ncell, cb = E.cell_base;
         if (ncell == 1) {
-            sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[cb], a.start[cb + 1], li, pos, 0.0f, me.x, 0.0f,
+            sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[cb], a.start[cb + 1], li, pos, 0.0f, me.x, 0.0f,
                                    me.y, true, L, r2, c2, K, nb, col);
         } else {
             const int reach = E.reach;
@@ -543,17 +564,17 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                 }
                 const int colb = cb + ccx * ncell;
                 if (lo < 0) {
-                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo + ncell], a.start[colb + ncell],
+                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo + ncell], a.start[colb + ncell],
                                            li, pos, offx, xi, -L, me.y, false, L, r2, c2, K, nb, col);
-                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi + 1], li, pos, offx,
+                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb], a.start[colb + hi + 1], li, pos, offx,
                                            xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
                 } else if (hi >= ncell) {
-                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + ncell], li, pos,
+                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo], a.start[colb + ncell], li, pos,
                                            offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
-                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb], a.start[colb + hi - ncell + 1],
+                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb], a.start[colb + hi - ncell + 1],
                                            li, pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, K, nb, col);
                 } else {
-                    sweep_run<A, G, kUnroll, kFov>(smin, a.sxy, a.start[colb + lo], a.start[colb + hi + 1], li, pos,
+                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo], a.start[colb + hi + 1], li, pos,
                                            offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
                 }
             }
@@ -572,14 +593,14 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     const int id = E.id_nxt[j];
     const float inv_r = E.inv_radius;
     float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
-    if (li == 0 && obs_dim > v) orow[v] = me.w;  // speed after the move (Sec. 4.1)
+    if (li == 0 && obs_dim > vs) orow[vs] = me.w;  // speed after the move (Sec. 4.1)
     if constexpr (G > 1) {
-        for (int k = li; k < v; k += G) {
+        for (int k = li; k < vs; k += G) {
             const uint32_t m = smin[k * A];
             orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
         }
-    } else if ((obs_dim & 3) == 0 && (v & 3) == 0) {
-        for (int k = 0; k < v; k += 4) {
+    } else if ((obs_dim & 3) == 0 && (vs & 3) == 0) {
+        for (int k = 0; k < vs; k += 4) {
             float o[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -590,13 +611,13 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
             *reinterpret_cast<float4 *>(orow + k) = make_float4(o[0], o[1], o[2], o[3]);
         }
     } else {
-        for (int k = 0; k < v; ++k) {
+        for (int k = 0; k < vs; ++k) {
             const uint32_t m = smin[k * A];
             orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
         }
     }
     if (li != 0) return;
-    const float r = E.r_nb * (float)nb + E.r_col * (float)col;
+    const float r = (kTag && ti) ? E.r_catch * (float)col : E.r_nb * (float)nb + E.r_col * (float)col;
     if (reward) reward[E.agent_base + id] = r;
     else if (E.rew) E.rew[id] = r;
     if (add_ret) E.ret_nxt[j] += (double)r;
@@ -661,6 +682,7 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
     a->sxy = cv.take<float2>(G);
+    a->stype = cv.take<uint8_t>(G);
     a->count = cv.take<int32_t>(C);
     a->start = cv.take<int32_t>(C + 1);
     a->part = cv.take<int32_t>(nb + 1);
@@ -678,18 +700,25 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
 }
 
 namespace {
+template <int NT, int G, bool kFov, bool kTag>
+void launch_sweep_v(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
+                    int add_return, hipStream_t s) {
+    constexpr int A = NT / G;
+    const size_t lds = (size_t)(kTag ? 2 : 1) * p.v * A * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag>), dim3(blocks_for(Gtot, A)), dim3(NT), lds, s,
+                       p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return);
+}
+
 template <int NT, int G>
 void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
                   int add_return, hipStream_t s) {
-    constexpr int A = NT / G;
-    const size_t lds = (size_t)p.v * A * sizeof(uint32_t);
-    const dim3 grid(blocks_for(Gtot, A));
-    if (p.fov)
-        hipLaunchKernelGGL((k_sweep<NT, G, true>), grid, dim3(NT), lds, s, p.a, envs, p.n_envs, Gtot,
-                           p.v, p.obs_dim, obs, reward, add_return);
-    else
-        hipLaunchKernelGGL((k_sweep<NT, G, false>), grid, dim3(NT), lds, s, p.a, envs, p.n_envs,
-                           Gtot, p.v, p.obs_dim, obs, reward, add_return);
+    if (p.tag) {
+        if (p.fov) launch_sweep_v<NT, G, true, true>(p, envs, Gtot, obs, reward, add_return, s);
+        else launch_sweep_v<NT, G, false, true>(p, envs, Gtot, obs, reward, add_return, s);
+    } else {
+        if (p.fov) launch_sweep_v<NT, G, true, false>(p, envs, Gtot, obs, reward, add_return, s);
+        else launch_sweep_v<NT, G, false, false>(p, envs, Gtot, obs, reward, add_return, s);
+    }
 }
 }  // namespace
 
@@ -712,13 +741,13 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
                            p.a.part, p.a.start, C);
     }
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G, p.tag);
     if (ev) (void)hipEventRecord(ev[3], s);
     const int lanes = p.lanes;
     if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s);
     else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s);
     else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s);
-    else if (p.v <= 32) launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
+    else if ((p.tag ? 2 * p.v : p.v) <= 32) launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
     else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s);
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();

@@ -81,17 +81,40 @@ __device__ __forceinline__ int env_of_row(const int32_t *base, int n_envs, int64
     return lo;
 }
 
+// What the output layer produces.
+enum PolOut {
+    kMean = 0,    // actor: the mean action, tanh-squashed and scaled
+    kSample = 1,  // actor: mean + sigma * eps and the Gaussian log density of the sample
+    kValue = 2,   // critic: the linear first output
+};
+
+// Per-launch sampling / value arguments (unused fields are ignored).
+struct OutArgs {
+    const float2 *eps;  // [n] standard-normal draws (kSample)
+    float sig0, sig1;   // exp(log_std) per action dimension
+    float logp_c;       // -(log_std0 + log_std1) - log(2 pi)
+    float *logp;        // [n] log density of the sample (kSample, may be null)
+    float *val;         // [n] critic value (kValue)
+    // Tag type filter: when type_want >= 0 only rows of that type (1 chaser,
+    // 0 runner; found through the batch tables) are computed and written.
+    int type_want;
+    const DevEnv *tenvs;
+    const int32_t *tbase;
+    int tn_envs;
+};
+
 // Rows are agents; obs/act are [n][in_dim] / [n][2] arrays, or, when `envs`
 // is non-null, each row's env-owned rows found through the batch tables.
 // kLdsW1: the layer-1 A operand (kc1 > kRegChunks chunks of 16 inputs) is
 // staged in dynamic LDS once per block instead of living in registers.
-template <bool kLdsW1>
+template <bool kLdsW1, int kOut>
 __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
                                                       float max_turn, float max_dspeed,
                                                       const float *__restrict__ obs, int64_t n,
                                                       float2 *__restrict__ act,
                                                       const DevEnv *__restrict__ envs,
-                                                      const int32_t *__restrict__ base, int n_envs) {
+                                                      const int32_t *__restrict__ base, int n_envs,
+                                                      OutArgs oa) {
     __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
     extern __shared__ bf16x8 s_w1[];  // [kc1][2 tiles][64 lanes] when kLdsW1
     if (kLdsW1)
@@ -121,7 +144,14 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
     for (int64_t tile = (int64_t)blockIdx.x * (kPolBlock / 64) + threadIdx.x / 64; tile < tiles;
          tile += waves) {
         const int64_t agent = tile * 32 + col;
-        const bool valid = agent < n;
+        bool valid = agent < n;
+        if (oa.type_want >= 0) {
+            if (valid) {
+                const DevEnv &T = oa.tenvs[env_of_row(oa.tbase, oa.tn_envs, agent)];
+                valid = ((agent - T.agent_base) < T.n_chasers ? 1 : 0) == oa.type_want;
+            }
+            if (!__any(valid)) continue;  // no row of this type in the tile
+        }
         const float *orow = obs + agent * in_dim;
         float2 *arow = act + agent;
         if (envs && valid) {
@@ -181,8 +211,20 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             }
         z0 = z0 + __shfl_xor(z0, 32, 64);
         z1 = z1 + __shfl_xor(z1, 32, 64);
-        if (g == 0 && valid)
-            *arow = make_float2(max_turn * tanhf(z0 + s_b3[0]), max_dspeed * tanhf(z1 + s_b3[1]));
+        if (g == 0 && valid) {
+            if constexpr (kOut == kValue) {
+                oa.val[agent] = z0 + s_b3[0];
+            } else {
+                float2 a = make_float2(max_turn * tanhf(z0 + s_b3[0]), max_dspeed * tanhf(z1 + s_b3[1]));
+                if constexpr (kOut == kSample) {
+                    const float2 e = oa.eps[agent];
+                    a.x = a.x + oa.sig0 * e.x;
+                    a.y = a.y + oa.sig1 * e.y;
+                    if (oa.logp) oa.logp[agent] = -0.5f * (e.x * e.x + e.y * e.y) + oa.logp_c;
+                }
+                *arow = a;
+            }
+        }
     }
 }
 
@@ -209,6 +251,7 @@ using namespace flock;
 
 struct flock_policy {
     int in_dim, kc1;
+    int critic;  // 0 actor (two scaled tanh outputs), 1 critic (one linear output)
     float max_turn, max_dspeed;
     PolLayout lay;
     std::vector<char> host;  // staged device image, kept until pol_destroy
@@ -218,42 +261,80 @@ namespace flock {
 
 namespace {
 size_t w1_lds_bytes(int kc1) { return (size_t)kc1 * 2 * 64 * sizeof(bf16x8); }
+
+OutArgs no_filter() {
+    OutArgs oa{};
+    oa.type_want = -1;
+    return oa;
+}
+
+template <int kOut>
+hipError_t launch_pol(const pol_t *p, const float *obs, int64_t n, float *act, const DevEnv *envs,
+                      const int32_t *base, int n_envs, const OutArgs &oa, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    float2 *a2 = reinterpret_cast<float2 *>(act);
+    if (p->kc1 > kRegChunks)
+        hipLaunchKernelGGL((k_policy<true, kOut>), dim3((unsigned)blocks), dim3(kPolBlock),
+                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
+                           p->max_dspeed, obs, n, a2, envs, base, n_envs, oa);
+    else
+        hipLaunchKernelGGL((k_policy<false, kOut>), dim3((unsigned)blocks), dim3(kPolBlock), 0, s,
+                           p->lay, p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n, a2, envs,
+                           base, n_envs, oa);
+    return hipGetLastError();
+}
 }  // namespace
 
 hipError_t policy_launch(const pol_t *p, const float *obs, int64_t n, float *act, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int64_t tiles = (n + 31) / 32;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
-    if (p->kc1 > kRegChunks)
-        hipLaunchKernelGGL(k_policy<true>, dim3((unsigned)blocks), dim3(kPolBlock),
-                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
-                           p->max_dspeed, obs, n, reinterpret_cast<float2 *>(act), nullptr, nullptr,
-                           0);
-    else
-        hipLaunchKernelGGL(k_policy<false>, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay,
-                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n,
-                           reinterpret_cast<float2 *>(act), nullptr, nullptr, 0);
-    return hipGetLastError();
+    return launch_pol<kMean>(p, obs, n, act, nullptr, nullptr, 0, no_filter(), s);
+}
+
+hipError_t policy_launch_sample(const pol_t *p, const float *obs, int64_t n, const float *eps,
+                                const float log_std[2], float *act, float *logp, hipStream_t s) {
+    OutArgs oa = no_filter();
+    oa.eps = reinterpret_cast<const float2 *>(eps);
+    oa.sig0 = (float)exp((double)log_std[0]);
+    oa.sig1 = (float)exp((double)log_std[1]);
+    oa.logp_c = (float)(-((double)log_std[0] + (double)log_std[1]) - log(2.0 * M_PI));
+    oa.logp = logp;
+    return launch_pol<kSample>(p, obs, n, act, nullptr, nullptr, 0, oa, s);
+}
+
+hipError_t policy_launch_value(const pol_t *p, const float *obs, int64_t n, float *val,
+                               hipStream_t s) {
+    OutArgs oa = no_filter();
+    oa.val = val;
+    return launch_pol<kValue>(p, obs, n, nullptr, nullptr, nullptr, 0, oa, s);
+}
+
+hipError_t policy_launch_typed(const pol_t *p, const StepPlan &plan, int table, int type,
+                               const float *obs, const float *eps, const float *log_std,
+                               float *act, float *logp, hipStream_t s) {
+    OutArgs oa{};
+    oa.type_want = type;
+    oa.tenvs = plan.a.envs[table & 1];
+    oa.tbase = plan.a.base;
+    oa.tn_envs = plan.n_envs;
+    if (!eps) return launch_pol<kMean>(p, obs, plan.G, act, nullptr, nullptr, 0, oa, s);
+    oa.eps = reinterpret_cast<const float2 *>(eps);
+    oa.sig0 = (float)exp((double)log_std[0]);
+    oa.sig1 = (float)exp((double)log_std[1]);
+    oa.logp_c = (float)(-((double)log_std[0] + (double)log_std[1]) - log(2.0 * M_PI));
+    oa.logp = logp;
+    return launch_pol<kSample>(p, obs, plan.G, act, nullptr, nullptr, 0, oa, s);
 }
 
 hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, int table, hipStream_t s) {
-    const int64_t n = plan.G;
-    if (n <= 0) return hipSuccess;
-    const int64_t tiles = (n + 31) / 32;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
-    if (p->kc1 > kRegChunks)
-        hipLaunchKernelGGL(k_policy<true>, dim3((unsigned)blocks), dim3(kPolBlock),
-                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
-                           p->max_dspeed, nullptr, n, nullptr, plan.a.envs[table & 1], plan.a.base,
-                           plan.n_envs);
-    else
-        hipLaunchKernelGGL(k_policy<false>, dim3((unsigned)blocks), dim3(kPolBlock), 0, s, p->lay,
-                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, nullptr, n, nullptr,
-                           plan.a.envs[table & 1], plan.a.base, plan.n_envs);
-    return hipGetLastError();
+    return launch_pol<kMean>(p, nullptr, plan.G, nullptr, plan.a.envs[table & 1], plan.a.base,
+                             plan.n_envs, no_filter(), s);
 }
+
+int policy_is_critic(const pol_t *p) { return p->critic; }
+
+const void *policy_weights(const pol_t *p) { return p->lay.w1f; }
 
 int policy_in_dim(const pol_t *p) { return p->in_dim; }
 
@@ -269,8 +350,13 @@ size_t pol_workspace_bytes(int in_dim, int hidden) {
     return carve_pol(nullptr, (in_dim + 15) / 16).bytes;
 }
 
-int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max_dspeed, void *ws,
-               size_t bytes, void *stream, pol_t **out) {
+}  // extern "C"
+
+namespace {
+
+// Shared by the actor (n_out = 2) and the critic (n_out = 1).
+int create_net(const float *w, int in_dim, int hidden, int n_out, float max_turn, float max_dspeed,
+               void *ws, size_t bytes, void *stream, pol_t **out) {
     if (!w || !ws || !out) return set_error(ENV_EINVAL, "NULL argument to pol_create");
     if (in_dim < 1 || in_dim > kMaxIn || hidden != kHidden)
         return set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= %d and hidden == 64", kMaxIn);
@@ -286,6 +372,7 @@ int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max
     pol_t *p = new pol_t;
     p->in_dim = in_dim;
     p->kc1 = kc1;
+    p->critic = n_out == 1 ? 1 : 0;
     p->max_turn = max_turn;
     p->max_dspeed = max_dspeed;
     p->lay = carve_pol(static_cast<char *>(ws), kc1);
@@ -301,7 +388,7 @@ int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max
     const float *W2 = b1 + H;
     const float *b2 = W2 + H * H;
     const float *W3 = b2 + H;
-    const float *b3 = W3 + H * 2;
+    const float *b3 = W3 + H * n_out;
     // layer-1 A operand: lane (g, col), element j = W1[16 kc + 8 g + j][32 t + col]
     uint16_t *w1f = reinterpret_cast<uint16_t *>(at(off.w1f));
     for (int kc = 0; kc < kc1; ++kc)
@@ -334,11 +421,12 @@ int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max
                 b1l[(t * 2 + g) * 16 + r] = b1[h];
                 b2l[(t * 2 + g) * 16 + r] = b2[h];
                 for (int o = 0; o < 2; ++o)
-                    w3l[((o * 2 + t) * 2 + g) * 16 + r] = bf16_round(W3[h * 2 + o]);
+                    w3l[((o * 2 + t) * 2 + g) * 16 + r] =
+                        o < n_out ? bf16_round(W3[h * n_out + o]) : 0.0f;
             }
     float *b3d = reinterpret_cast<float *>(at(off.b3));
     b3d[0] = b3[0];
-    b3d[1] = b3[1];
+    b3d[1] = n_out > 1 ? b3[1] : 0.0f;
     hipError_t e = hipMemcpyAsync(ws, hb, need, hipMemcpyHostToDevice,
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) {
@@ -349,14 +437,53 @@ int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max
     return ENV_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pol_create(const float *w, int in_dim, int hidden, float max_turn, float max_dspeed, void *ws,
+               size_t bytes, void *stream, pol_t **out) {
+    return create_net(w, in_dim, hidden, 2, max_turn, max_dspeed, ws, bytes, stream, out);
+}
+
+int pol_create_value(const float *w, int in_dim, int hidden, void *ws, size_t bytes, void *stream,
+                     pol_t **out) {
+    return create_net(w, in_dim, hidden, 1, 1.0f, 1.0f, ws, bytes, stream, out);
+}
+
 void pol_destroy(pol_t *p) { delete p; }
 
 int pol_forward(pol_t *p, const float *obs, int64_t n, float *act, void *stream) {
     if (!p) return set_error(ENV_EINVAL, "policy is NULL");
+    if (p->critic) return set_error(ENV_EINVAL, "pol_forward needs an actor (this is a critic)");
     if (n < 0) return set_error(ENV_EINVAL, "n < 0");
     if (n > 0 && (!obs || !act)) return set_error(ENV_EINVAL, "obs/act is NULL");
     hipError_t e = policy_launch(p, obs, n, act, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return set_error(ENV_EHIP, "pol_forward: %s", hipGetErrorString(e));
+    return ENV_OK;
+}
+
+int pol_sample(pol_t *p, const float *obs, int64_t n, const float *log_std, const float *eps,
+               float *act, float *logp, void *stream) {
+    if (!p || !log_std) return set_error(ENV_EINVAL, "policy or log_std is NULL");
+    if (p->critic) return set_error(ENV_EINVAL, "pol_sample needs an actor (this is a critic)");
+    if (n < 0) return set_error(ENV_EINVAL, "n < 0");
+    if (!isfinite(log_std[0]) || !isfinite(log_std[1]))
+        return set_error(ENV_EINVAL, "log_std must be finite");
+    if (n > 0 && (!obs || !eps || !act)) return set_error(ENV_EINVAL, "obs/eps/act is NULL");
+    hipError_t e = policy_launch_sample(p, obs, n, eps, log_std, act, logp,
+                                        reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(ENV_EHIP, "pol_sample: %s", hipGetErrorString(e));
+    return ENV_OK;
+}
+
+int pol_value(pol_t *p, const float *obs, int64_t n, float *value, void *stream) {
+    if (!p) return set_error(ENV_EINVAL, "critic is NULL");
+    if (!p->critic) return set_error(ENV_EINVAL, "pol_value needs a critic (pol_create_value)");
+    if (n < 0) return set_error(ENV_EINVAL, "n < 0");
+    if (n > 0 && (!obs || !value)) return set_error(ENV_EINVAL, "obs/value is NULL");
+    hipError_t e = policy_launch_value(p, obs, n, value, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(ENV_EHIP, "pol_value: %s", hipGetErrorString(e));
     return ENV_OK;
 }
 

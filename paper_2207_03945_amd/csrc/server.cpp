@@ -280,6 +280,7 @@ int srv_create(void *arena, size_t arena_bytes, int max_slots, pol_t *pol, void 
     if (reinterpret_cast<uintptr_t>(arena) % 256 != 0)
         return set_error(ENV_EINVAL, "arena must be 256-byte aligned");
     if (max_slots < 1) return set_error(ENV_EINVAL, "max_slots must be >= 1");
+    if (policy_is_critic(pol)) return set_error(ENV_EINVAL, "the server needs an actor, not a critic");
     srv_t *S = new srv_t;
     S->arena = static_cast<char *>(arena);
     S->arena_bytes = arena_bytes;
@@ -303,6 +304,8 @@ int srv_submit(srv_t *S, const env_params_t *p, const float *x, const float *y, 
     if (!S || !id) return set_error(ENV_EINVAL, "NULL argument to srv_submit");
     int rc = validate_params(p);
     if (rc != ENV_OK) return rc;
+    if (p->flags & ENV_FLAG_TAG)
+        return set_error(ENV_EINVAL, "the server runs flock requests (one shared policy), not tag");
     if (obs_dim_of(*p) != policy_in_dim(S->pol))
         return set_error(ENV_EINVAL, "request observations have %d values, policy takes %d",
                          obs_dim_of(*p), policy_in_dim(S->pol));

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libflockenv.so")
 ENV_OK, ENV_EINVAL, ENV_ENOMEM, ENV_ESTATE, ENV_EHIP, ENV_EAGAIN, ENV_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 ENV_FLAG_COUNTS = 1
 ENV_FLAG_SPEED_OBS = 2
+ENV_FLAG_TAG = 4
 
 _CODES = {ENV_EINVAL: "ENV_EINVAL", ENV_ENOMEM: "ENV_ENOMEM", ENV_ESTATE: "ENV_ESTATE",
           ENV_EHIP: "ENV_EHIP", ENV_EAGAIN: "ENV_EAGAIN", ENV_ENOTFOUND: "ENV_ENOTFOUND"}
@@ -35,7 +36,8 @@ class EnvParams(ctypes.Structure):
                 ("collide", ctypes.c_float), ("sectors", ctypes.c_int32), ("r_nb", ctypes.c_float),
                 ("r_col", ctypes.c_float), ("max_turn", ctypes.c_float),
                 ("max_dspeed", ctypes.c_float), ("s_min", ctypes.c_float), ("s_max", ctypes.c_float),
-                ("cell_reach", ctypes.c_int32), ("flags", ctypes.c_int32), ("fov", ctypes.c_float)]
+                ("cell_reach", ctypes.c_int32), ("flags", ctypes.c_int32), ("fov", ctypes.c_float),
+                ("n_chasers", ctypes.c_int32), ("r_catch", ctypes.c_float)]
 
 
 @dataclass
@@ -55,11 +57,14 @@ class Params:
     cell_reach: int = 0
     flags: int = 0
     fov: float = 0.0   # view arc in radians; 0 = full circle
+    n_chasers: int = 0  # tag envs (ENV_FLAG_TAG): agents 0 .. n_chasers-1 chase
+    r_catch: float = 1.0  # tag: chaser reward per runner touched
 
     @property
     def obs_dim(self) -> int:
-        """Length of a view row: the sectors, then the speed with ENV_FLAG_SPEED_OBS."""
-        return self.sectors + (1 if self.flags & ENV_FLAG_SPEED_OBS else 0)
+        """Length of a view row: the sectors (two channels for tag), then the speed."""
+        channels = 2 if self.flags & ENV_FLAG_TAG else 1
+        return channels * self.sectors + (1 if self.flags & ENV_FLAG_SPEED_OBS else 0)
 
     def c(self) -> EnvParams:
         return EnvParams(*[getattr(self, f.name) for f in fields(self)])
@@ -112,6 +117,18 @@ def lib():
         "pol_destroy": (None, [_P]),
         "pol_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
         "env_step_policy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+        "pol_create_value": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t,
+                                            _P, _PP]),
+        "pol_value": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+        "pol_sample": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+        "env_rollout": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]),
+        "env_rollout_tag": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]),
+        "env_step_policy_tag": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "rl_gae": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                  _P, _P, _P, _P, _P]),
+        "gr_opinion_step": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, _P, _P, _P,
+                                           ctypes.c_float, ctypes.c_float, _P, _P, ctypes.c_int,
+                                           _P]),
         "srv_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int, _P, _P, _PP]),
         "srv_destroy": (None, [_P]),
         "srv_submit": (ctypes.c_int, [_P, ep, _P, _P, _P, _P, ctypes.c_int,
@@ -313,6 +330,51 @@ class Batch:
         check(lib().env_batch_run(self.handle, k_steps, _ptr(act), _ptr(obs), _ptr(reward),
                                   _stream(stream)))
 
+    def rollout(self, policy, steps, obs, act, reward, logp=None, eps=None, log_std=None,
+                stream=None):
+        """`steps` closed-loop steps into rollout buffers (env_rollout of the C ABI).
+
+        obs [steps + 1, G, d] (block 0 = current view), act [steps, G, 2],
+        reward [steps, G], logp [steps, G] or None; eps [steps, G, 2] standard
+        normals and log_std (2 floats) for Gaussian sampling, or None for the
+        mean action.  ``stream`` must be a non-default torch stream.
+        """
+        _dev_f32(obs, (steps + 1, self.n, self.d), "obs")
+        _dev_f32(act, (steps, self.n, 2), "act")
+        _dev_f32(reward, (steps, self.n), "reward")
+        if logp is not None:
+            _dev_f32(logp, (steps, self.n), "logp")
+        ls = None
+        if eps is not None:
+            _dev_f32(eps, (steps, self.n, 2), "eps")
+            ls = (ctypes.c_float * 2)(*[float(x) for x in log_std])
+        check(lib().env_rollout(self.handle, policy.handle, int(steps), ls, _ptr(eps), _ptr(obs),
+                                _ptr(act), _ptr(logp), _ptr(reward), _stream(stream)))
+
+    def rollout_tag(self, runner, chaser, steps, obs, act, reward, logp=None, eps=None,
+                    log_std=None, stream=None):
+        """Tag rollout: as ``rollout`` with a policy per type; log_std = 4 floats
+        (runner's two, then the chaser's)."""
+        _dev_f32(obs, (steps + 1, self.n, self.d), "obs")
+        _dev_f32(act, (steps, self.n, 2), "act")
+        _dev_f32(reward, (steps, self.n), "reward")
+        if logp is not None:
+            _dev_f32(logp, (steps, self.n), "logp")
+        ls = None
+        if eps is not None:
+            _dev_f32(eps, (steps, self.n, 2), "eps")
+            ls = (ctypes.c_float * 4)(*[float(x) for x in log_std])
+        check(lib().env_rollout_tag(self.handle, runner.handle, chaser.handle, int(steps), ls,
+                                    _ptr(eps), _ptr(obs), _ptr(act), _ptr(logp), _ptr(reward),
+                                    _stream(stream)))
+
+    def step_policy_tag(self, runner, chaser, act, obs, reward, stream=None):
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.d), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        check(lib().env_step_policy_tag(self.handle, runner.handle, chaser.handle, _ptr(act),
+                                        _ptr(obs), _ptr(reward), _stream(stream)))
+
     def step_policy(self, policy, act, obs, reward, stream=None):
         _dev_f32(act, (self.n, 2), "act")
         _dev_f32(obs, (self.n, self.d), "obs")
@@ -362,6 +424,97 @@ class Policy:
         _dev_f32(act, (n, 2), "act")
         check(lib().pol_forward(self.handle, _ptr(obs), n, _ptr(act), _stream(stream)))
         return act
+
+
+    def sample(self, obs, eps, log_std, act=None, logp=None, stream=None):
+        """Gaussian actions round the mean: (act [n, 2], logp [n])."""
+        n = obs.shape[0]
+        if act is None:
+            act = torch.empty(n, 2, dtype=torch.float32, device=obs.device)
+        if logp is None:
+            logp = torch.empty(n, dtype=torch.float32, device=obs.device)
+        _dev_f32(obs, (n, self.in_dim), "obs")
+        _dev_f32(eps, (n, 2), "eps")
+        _dev_f32(act, (n, 2), "act")
+        _dev_f32(logp, (n,), "logp")
+        ls = (ctypes.c_float * 2)(*[float(x) for x in log_std])
+        check(lib().pol_sample(self.handle, _ptr(obs), n, ls, _ptr(eps), _ptr(act), _ptr(logp),
+                               _stream(stream)))
+        return act, logp
+
+
+class Critic:
+    """Value network (in -> 64 -> 64 -> 1, tanh hidden, linear output) in BF16 on MFMA."""
+
+    def __init__(self, weights, biases, device="cuda", stream=None):
+        in_dim, hidden = weights[0].shape
+        self.in_dim, self.hidden = int(in_dim), int(hidden)
+        self._host = pack_policy_weights(weights, biases)
+        nbytes = lib().pol_workspace_bytes(self.in_dim, self.hidden)
+        if nbytes == 0:
+            raise FlockError(ENV_EINVAL, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(lib().pol_create_value(self._host.ctypes.data, self.in_dim, self.hidden,
+                                     self.workspace.data_ptr(), nbytes, _stream(stream),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.pol_destroy(h)
+            self.handle = None
+
+    def value(self, obs, out=None, stream=None):
+        """V [n] for obs [n, in_dim] (any leading shape is flattened to rows)."""
+        rows = obs.reshape(-1, self.in_dim)
+        n = rows.shape[0]
+        if out is None:
+            out = torch.empty(obs.shape[:-1], dtype=torch.float32, device=obs.device)
+        _dev_f32(rows, (n, self.in_dim), "obs")
+        if not (out.is_contiguous() and out.numel() == n and out.dtype == torch.float32):
+            raise ValueError("out must be a contiguous float32 tensor with one value per row")
+        check(lib().pol_value(self.handle, _ptr(rows), n, _ptr(out), _stream(stream)))
+        return out
+
+
+def gae(reward, value, gamma, lam, adv=None, ret=None, stream=None):
+    """Truncated advantage estimator over [steps, n] rewards and [steps + 1, n] values."""
+    steps, n = reward.shape
+    if adv is None:
+        adv = torch.empty_like(reward)
+    if ret is None:
+        ret = torch.empty_like(reward)
+    _dev_f32(reward, (steps, n), "reward")
+    _dev_f32(value, (steps + 1, n), "value")
+    _dev_f32(adv, (steps, n), "adv")
+    _dev_f32(ret, (steps, n), "ret")
+    check(lib().rl_gae(int(steps), int(n), float(gamma), float(lam), _ptr(reward), _ptr(value),
+                       _ptr(adv), _ptr(ret), _stream(stream)))
+    return adv, ret
+
+
+def opinion_step(row_ptr, col, weight, op_in, op_out, threshold, strength, lanes=0,
+                 stream=None):
+    """One step of the opinion-dynamics graph interaction (gr_opinion_step of the C ABI).
+
+    row_ptr int64 [n + 1], col int32 [E], weight float32 [E], op_in/op_out
+    float32 [n] (distinct), all CUDA tensors.
+    """
+    n = op_in.shape[0]
+    E = col.shape[0]
+    for t, dt, shape, nm in ((row_ptr, torch.int64, (n + 1,), "row_ptr"),
+                             (col, torch.int32, (E,), "col"), (weight, torch.float32, (E,), "weight"),
+                             (op_in, torch.float32, (n,), "op_in"),
+                             (op_out, torch.float32, (n,), "op_out")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()
+                and tuple(t.shape) == shape):
+            raise TypeError(f"{nm} must be a contiguous CUDA {dt} tensor of shape {shape}")
+    check(lib().gr_opinion_step(n, E, _ptr(row_ptr), _ptr(col), _ptr(weight), float(threshold),
+                                float(strength), _ptr(op_in), _ptr(op_out), int(lanes),
+                                _stream(stream)))
+    return op_out
 
 
 def request_bytes(params: Params) -> int:

@@ -45,7 +45,8 @@ def _bytes(**kw):
     dict(collide=-0.1), dict(collide=9.0), dict(sectors=0), dict(sectors=257),
     dict(r_nb=math.nan), dict(max_turn=-0.1), dict(max_dspeed=math.inf), dict(s_min=-1.0),
     dict(s_min=3.0, s_max=2.0), dict(cell_reach=3), dict(cell_reach=-1), dict(flags=8),
-    dict(flags=4), dict(fov=-0.1), dict(fov=6.3), dict(fov=math.nan), dict(fov=math.inf),
+    dict(flags=16), dict(flags=4, n_chasers=-1), dict(flags=4, n_chasers=300),
+    dict(flags=4, r_catch=math.nan), dict(flags=4, sectors=129), dict(fov=-0.1), dict(fov=6.3), dict(fov=math.nan), dict(fov=math.inf),
 ])
 def test_invalid_params_rejected(kw):
     assert _bytes(**kw) == 0
@@ -56,7 +57,9 @@ def test_invalid_params_rejected(kw):
                                 dict(radius=31.99), dict(collide=0.0), dict(cell_reach=2),
                                 dict(flags=1), dict(flags=2), dict(flags=3),
                                 dict(fov=math.radians(250.0)), dict(fov=1e-3),
-                                dict(fov=float(np.float32(2 * math.pi)))])
+                                dict(fov=float(np.float32(2 * math.pi))),
+                                dict(flags=4, n_chasers=23, sectors=64),
+                                dict(flags=6, n_chasers=0, sectors=128)])
 def test_valid_params_accepted(kw):
     assert _bytes(**kw) > 0
 
@@ -131,6 +134,10 @@ def test_batch_validation_without_gpu():
     rc3, h3, _ = _create(sectors=16, flags=fe.ENV_FLAG_SPEED_OBS)
     arr[1] = h3.value
     assert lib.env_batch_workspace_bytes(pp, 2) == 0 and "SPEED_OBS" in fe.last_error()
+    rc5, h5, _ = _create(sectors=16, flags=fe.ENV_FLAG_TAG, n_chasers=10)
+    arr[1] = h5.value   # tag and flock envs do not mix
+    assert lib.env_batch_workspace_bytes(pp, 2) == 0 and "TAG" in fe.last_error()
+    lib.env_destroy(h5)
     rc4, h4, _ = _create(sectors=16, fov=math.radians(250.0))
     arr[1] = h4.value   # fields of view may differ within a batch
     assert lib.env_batch_workspace_bytes(pp, 2) > 0
@@ -177,10 +184,46 @@ def test_sweep_lanes_validation_without_gpu():
     lib.env_destroy(h)
 
 
+def test_rl_validation_without_gpu():
+    lib = fe.lib()
+    buf = 1 << 20
+    assert lib.rl_gae(0, 10, 0.99, 0.95, buf, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, -1, 0.99, 0.95, buf, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, 10, 1.5, 0.95, buf, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, 10, 0.99, -0.1, buf, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, 10, math.nan, 0.9, buf, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, 10, 0.99, 0.95, None, buf, buf, buf, None) == fe.ENV_EINVAL
+    assert lib.rl_gae(4, 0, 0.99, 0.95, None, None, None, None, None) == fe.ENV_OK
+    h = ctypes.c_void_p()
+    w = (ctypes.c_float * 20000)()
+    assert lib.pol_create_value(None, 16, 64, 1 << 20, 1 << 20, None, ctypes.byref(h)) == fe.ENV_EINVAL
+    assert lib.pol_create_value(w, 300, 64, 1 << 20, 1 << 20, None, ctypes.byref(h)) == fe.ENV_EINVAL
+    assert lib.pol_create_value(w, 16, 64, 1 << 20, 10, None, ctypes.byref(h)) == fe.ENV_ENOMEM
+    assert lib.pol_value(None, None, 0, None, None) == fe.ENV_EINVAL
+    assert lib.pol_sample(None, None, 0, None, None, None, None, None) == fe.ENV_EINVAL
+    assert lib.env_rollout(None, None, 4, None, None, None, None, None, None, None) == fe.ENV_EINVAL
+
+
+def test_graph_validation_without_gpu():
+    lib = fe.lib()
+    b = 1 << 20
+    assert lib.gr_opinion_step(-1, 0, b, b, b, 0.3, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(1 << 31, 0, b, b, b, 0.3, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, -1, b, b, b, 0.3, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, 5, b, b, b, math.nan, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, 5, b, b, b, 0.3, 0.5, b, b + 64, 2, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, 5, None, b, b, 0.3, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, 5, b, None, b, 0.3, 0.5, b, b + 64, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(10, 5, b, b, b, 0.3, 0.5, b, b, 0, None) == fe.ENV_EINVAL
+    assert lib.gr_opinion_step(0, 0, None, None, None, 0.3, 0.5, None, None, 0, None) == fe.ENV_OK
+
+
 def test_obs_dim():
     assert fe.Params(n_agents=4, box=64.0, sectors=128).obs_dim == 128
     assert fe.Params(n_agents=4, box=64.0, sectors=128, flags=fe.ENV_FLAG_SPEED_OBS).obs_dim == 129
     assert fe.Params(n_agents=4, box=64.0, flags=3).obs_dim == 17
+    assert fe.Params(n_agents=4, box=64.0, sectors=64, flags=fe.ENV_FLAG_TAG).obs_dim == 128
+    assert fe.Params(n_agents=4, box=64.0, sectors=64, flags=6).obs_dim == 129
 
 
 def test_missing_library_raises(tmp_path, monkeypatch):

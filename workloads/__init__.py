@@ -14,6 +14,9 @@ Workloads (all FP32, periodic square box of side L):
   * uneven env sizes: N_e = round(exp(U[ln lo, ln hi])), side L_e = 4 sqrt(N_e)
   * arrivals: Poisson process (exponential gaps) for the serving loop
   * policy noise: standard normals [steps, n, 2] for Gaussian action sampling
+  * paper tag (Sec. 4.2, 5): a chaser per ten runners (agents 0 .. n/11 - 1
+    chase), two view channels of 64 sectors, 250 degrees, vision L/10,
+    touch distance 1; uniform start; speeds U[0, 2) as the action
   * social graph: power-law degrees (exponent 2.5, 5..2,000, mean about 14),
     configuration-model pairing, symmetric weights U[0, 1), opinions U[0, 1)
   * paper flock (Sec. 4.1, 5): v = 128 sectors, a field of view of 250
@@ -79,6 +82,14 @@ def blob_state(n: int, box: float, seed: int = 0, env: int = 0, n_blobs: int = 6
     th = _headings(g, n)
     s = np.full(n, speed, np.float32)
     return x, y, th, s
+
+
+def tag_actions(n: int, seed: int = 0, step: int = 0, env: int = 0, max_turn: float = 0.2,
+                s_max: float = 2.0) -> np.ndarray:
+    """Tag actions [n, 2] FP32: turn U[-max_turn, max_turn], speed U[0, s_max)."""
+    g = rng(seed, PURPOSE_ACTION, env, step)
+    a = g.random((n, 2))
+    return np.stack([(2.0 * a[:, 0] - 1.0) * max_turn, a[:, 1] * s_max], 1).astype(np.float32)
 
 
 def random_actions(n: int, seed: int = 0, step: int = 0, env: int = 0,
@@ -181,6 +192,12 @@ WORKLOADS = {
                           speed_obs=True, steps=128, init="uniform"),
     "paper_flock10k": dict(n=10000, box=100.0, radius=10.0, sectors=128, fov_deg=250.0,
                            speed_obs=True, steps=128, init="uniform"),
+    # the paper's tag settings: a chaser per ten runners, two channels of 64
+    # sectors, 250 degrees, vision L/10, touch distance 1
+    "paper_tag1k": dict(n=1100, chasers=100, box=100.0, radius=10.0, sectors=64, fov_deg=250.0,
+                        touch=1.0, steps=128, init="uniform"),
+    "paper_tag11k": dict(n=11000, chasers=1000, box=100.0, radius=10.0, sectors=64,
+                         fov_deg=250.0, touch=1.0, steps=128, init="uniform"),
 }
 
 

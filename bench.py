@@ -69,21 +69,24 @@ def make_envs(flock, workloads, n, box, count, init, seed0, **params):
     return envs
 
 
-def device_actions(G, K, seed):
+def device_actions(G, K, seed, tag=False):
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     a = torch.rand(K, G, 2, device="cuda", generator=g) * 2.0 - 1.0
     a[..., 0] *= 0.2
-    a[..., 1] *= 0.1
+    if tag:   # tag actions set the speed: U[0, 2)
+        a[..., 1] = (a[..., 1] + 1.0)
+    else:
+        a[..., 1] *= 0.1
     return a.contiguous()
 
 
-def bench_batched(flock, batch, K, W, seed, timed_reps=20):
+def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False):
     """Graph-replayed K-step run + per-phase timing; returns a dict."""
     import torch
     G = batch.n
-    act = device_actions(G, K, seed)
+    act = device_actions(G, K, seed, tag)
     obs = torch.empty(G, batch.d, device="cuda")
     rew = torch.empty(K, G, device="cuda")
     stream = torch.cuda.Stream()
@@ -118,9 +121,9 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20):
                          "scatter": float(ph[2]), "sweep": float(ph[3])}}
 
 
-def bench_plain(env, n, K, W, seed):
+def bench_plain(env, n, K, W, seed, tag=False):
     import torch
-    act = device_actions(n, K, seed)
+    act = device_actions(n, K, seed, tag)
     obs = torch.empty(n, env.d, device="cuda")
     rew = torch.empty(n, device="cuda")
     for t in range(W):
@@ -390,9 +393,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="run the main batched leg only")
-    ap.add_argument("--legs", default="plain,50k,uneven,paper,rollout,graph,serving",
-                    help="comma list of extra legs: plain, 50k, uneven, paper, rollout, graph, "
-                         "serving")
+    ap.add_argument("--legs", default="plain,50k,uneven,paper,tag,rollout,graph,serving",
+                    help="comma list of extra legs: plain, 50k, uneven, paper, tag, rollout, "
+                         "graph, serving")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
@@ -488,6 +491,30 @@ def main():
             "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"]),
             "sweep_hbm_frac": pf_bytes * b10.n / (bat["phase_ms"]["sweep"] * 1e-3) / HBM_PEAK}
         del b10, e10
+    if "tag" in legs:
+        log("[bench] tag 11k")
+        tg = workloads.WORKLOADS["paper_tag11k"]
+        tg_params = dict(sectors=tg["sectors"], radius=tg["radius"], collide=tg["touch"],
+                         fov=math.radians(tg["fov_deg"]), flags=flock.ENV_FLAG_TAG,
+                         n_chasers=tg["chasers"], r_catch=1.0)
+        tg_plist = [flock.Params(n_agents=tg["n"], box=tg["box"], **tg_params) for _ in range(20)]
+        tg_states = [workloads.uniform_state(tg["n"], tg["box"], seed=4000 + k) for k in range(20)]
+        tg_reach, tg_lanes, tg_ms = autotune.tune(tg_plist, tg_states, cache=None)
+        e11 = make_envs(flock, workloads, tg["n"], tg["box"], 20, "uniform", 4000,
+                        cell_reach=tg_reach, **tg_params)
+        e11[0].set_sweep_lanes(tg_lanes)
+        plain = bench_plain(e11[0], tg["n"], K, W, seed=8, tag=True)
+        b11 = flock.Batch(e11)
+        b11.set_sweep_lanes(tg_lanes)
+        bat = bench_batched(flock, b11, K, W, seed=9, timed_reps=10, tag=True)
+        work = sweep_work(e11)
+        extra["paper_tag11k"] = {
+            "workload": "20 envs x 11,000 agents (1,000 chasers), side 100, vision 10, two "
+                        "channels of 64 sectors, field of view 250 degrees, touch distance 1",
+            "cell_reach": tg_reach, "sweep_lanes": tg_lanes, "tuned_ms": tg_ms,
+            "plain": plain, "batched_x20": bat, "sweep_work_per_launch": work,
+            "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"])}
+        del b11, e11
     if "rollout" in legs:
         log("[bench] experience collection")
         extra["rollout"] = bench_rollout(flock, workloads)

@@ -80,7 +80,7 @@ struct StepPlan {
     int fov;      // any env of the plan has a limited view
     int lanes;    // lanes per agent in the sweep: 1, 4, 16 or 64
     int tag;      // the plan's envs are tag envs (two view channels)
-    int scan_blocks;  // 0 -> single-block scan
+    int scan_blocks;  // 0 -> one scan block per env (every env <= 16384 cells)
 };
 
 // Workspace carving --------------------------------------------------------
@@ -100,8 +100,9 @@ struct Carver {
     }
 };
 
-// Number of scan partial blocks for C cells (0 = one block does everything).
-int scan_blocks_for(int64_t C);
+// Tiles of the two-level scan over C cells, or 0 when every env has few
+// enough cells (max_env_cells) for one scan block per env.
+int scan_blocks_for(int64_t C, int64_t max_env_cells);
 // Carve the sort scratch for G agents, C cells and E envs.
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 

@@ -39,6 +39,8 @@
 //   * view: 1 - sqrt(d^2_min) * (1/R), within a few ulp of 1 - d_min/R.
 #include <limits.h>
 
+#include <type_traits>
+
 #include "flock_internal.h"
 
 namespace flock {
@@ -200,16 +202,25 @@ constexpr int kScanNT = 1024;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanNT * kScanItems;  // cells of the single-block scan
 
-// C <= kScanTile: one block does the whole scan and re-zeroes the counts.
-__global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ count,
-                                                         int32_t *__restrict__ start, int C) {
+// Every env has at most kScanTile cells: block e scans env e's cells on its
+// own.  An env's agents occupy cell-order positions [agent_base, agent_base
+// + n), so its cell starts are agent_base plus the prefix within the env;
+// no block waits for another.  Re-zeroes the counts; the last env's block
+// also writes start[C] (= the batch's agent total).
+__global__ __launch_bounds__(kScanNT) void k_scan_env(int32_t *__restrict__ count,
+                                                      int32_t *__restrict__ start,
+                                                      const DevEnv *__restrict__ envs, int n_envs,
+                                                      int C) {
     __shared__ int s_wave[kScanNT / 64 + 1];
     __shared__ int s_tile[kScanTile];
     const int t = threadIdx.x;
+    const DevEnv &E = envs[blockIdx.x];
+    const int cb = E.cell_base, Ce = E.ncell * E.ncell, base = E.agent_base;
+    count += cb;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int idx = k * kScanNT + t;  // coalesced: item-major
-        s_tile[idx] = idx < C ? count[idx] : 0;
+        s_tile[idx] = idx < Ce ? count[idx] : 0;
     }
     __syncthreads();
     int vals[kScanItems];
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ c
         sum += vals[k];
     }
     int total;
-    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total);
+    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total) + base;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         s_tile[t * kScanItems + k] = run;
@@ -230,12 +241,12 @@ __global__ __launch_bounds__(kScanNT) void k_scan_single(int32_t *__restrict__ c
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int idx = k * kScanNT + t;
-        if (idx < C) {
-            start[idx] = s_tile[idx];
+        if (idx < Ce) {
+            start[cb + idx] = s_tile[idx];
             count[idx] = 0;
         }
     }
-    if (t == 0) start[C] = total;
+    if (t == 0 && blockIdx.x == n_envs - 1) start[C] = base + total;
 }
 
 // Large C: tiles of kTile2 cells, one 256-thread block each.
@@ -395,6 +406,34 @@ __device__ __forceinline__ int sector_of(float dx, float dy, float c, float s, f
     return k < v - 1 ? k : v - 1;
 }
 
+// As sector_of for a full view with v = 8 M sectors (M sectors per octant),
+// without the arctangent: the octant comes from the signs and the larger of
+// |u| and |w|, the sector within it from comparing t = min/max with the
+// tangents of the octant's interior sector edges, and mirrored octants
+// count their sectors backwards.  A bearing exactly on an octant edge may
+// land in either neighbouring sector (both are within the ambiguity band).
+template <int M>
+__device__ __forceinline__ int sector_oct(float dx, float dy, float c, float s) {
+    const float u = __builtin_fmaf(dx, c, dy * s);
+    const float w = __builtin_fmaf(dy, c, -(dx * s));
+    const float au = fabsf(u), aw = fabsf(w);
+    int j = 0;
+    if constexpr (M > 1) {
+        const float mx = fmaxf(au, aw), mn = fminf(au, aw);
+        const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+        if constexpr (M == 2) {
+            j = t >= 0.41421356237309503f ? 1 : 0;  // tan(pi/8)
+        } else {
+            static_assert(M == 4, "sector_oct takes M = 1, 2 or 4");
+            j = (t >= 0.19891236737965800f ? 1 : 0) + (t >= 0.41421356237309503f ? 1 : 0) +
+                (t >= 0.66817863791929891f ? 1 : 0);  // tan(pi/16), tan(pi/8), tan(3 pi/16)
+        }
+    }
+    int k = aw > au ? 2 * M - 1 - j : j;
+    k = u < 0.0f ? 4 * M - 1 - k : k;
+    return w < 0.0f ? 8 * M - 1 - k : k;
+}
+
 // View sector of the bearing of (dx, dy) for a limited field of view: the
 // bearing in turns from the heading (as in sector_of), shifted by half the
 // arc and wrapped, is seen iff it lies in the arc; -1 when not seen.  A
@@ -447,7 +486,9 @@ struct ViewK {
 // kTag (tag environment): candidate q's type stype[q] picks the view channel
 // (minima at smin_own[(tj v + k) S]); nb counts runners in range and col
 // touches with the other type (the lane's own type is ti).
-template <int S, int G, int UNROLL, bool kFov, bool kTag>
+// kShiftX / kShiftY: the candidate-side shift offx / offy may be nonzero (a
+// zero shift is left out: x + 0 = x for the nonnegative coordinates here).
+template <int S, int G, int UNROLL, bool kFov, bool kTag, int kM, bool kShiftX, bool kShiftY>
 __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
                                           const uint8_t *__restrict__ stype, int ti,
                                           int q, int q1, int li, int self, float offx, float xi,
@@ -459,8 +500,8 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
             dx = min_image_delta(pj.x, xi, L);
             dy = min_image_delta(pj.y, yi, L);
         } else {
-            dx = (pj.x + offx) - xi;
-            dy = (pj.y + offy) - yi;
+            dx = (kShiftX ? pj.x + offx : pj.x) - xi;
+            dy = (kShiftY ? pj.y + offy : pj.y) - yi;
         }
         const float d2 = __builtin_fmaf(dx, dx, dy * dy);
         const bool nbr = d2 < r2 && qq != self;
@@ -478,7 +519,9 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
             const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
             if (nbr && k >= 0) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
         } else {
-            const int k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
+            int k;
+            if constexpr (kM > 0) k = sector_oct<kM>(dx, dy, K.c, K.s);
+            else k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
             if (nbr) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
         }
     };
@@ -503,7 +546,8 @@ constexpr int kUnroll = 4;
 // among a lane group, which keeps the lanes busy and the LDS per agent small.
 // kFov: some env of the launch has a limited field of view.  obs rows hold
 // obs_dim floats: the v sectors, then the speed when obs_dim > v.
-template <int NT, int G, bool kFov, bool kTag>
+// kM > 0: full view with v = 8 kM sectors (sector_oct); 0: any v.
+template <int NT, int G, bool kFov, bool kTag, int kM>
 __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
                                               int n_envs, int Gtot, int v, int obs_dim,
                                               float *__restrict__ obs, float *__restrict__ reward,
@@ -544,39 +588,45 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         ti = kTag ? (E.id_nxt[j] < E.n_chasers ? 1 : 0) : 0;
         const float L = E.box, r2 = E.r2, c2 = E.c2;
         const int ncell = E.ncell, cb = E.cell_base;
+        // one run of candidates [q, q1): template flags say which shifts are nonzero
+        auto run = [&](auto sx, auto sy, int q, int q1, float offx, float xi, float offy, float yi,
+                       bool minimg) {
+            sweep_run<A, G, kUnroll, kFov, kTag, kM, decltype(sx)::value, decltype(sy)::value>(
+                smin, a.sxy, a.stype, ti, q, q1, li, pos, offx, xi, offy, yi, minimg, L, r2, c2, K,
+                nb, col);
+        };
+        using No = std::false_type;
+        using Yes = std::true_type;
         if (ncell == 1) {
-            sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[cb], a.start[cb + 1], li, pos, 0.0f, me.x, 0.0f,
-                                   me.y, true, L, r2, c2, K, nb, col);
+            run(No{}, No{}, a.start[cb], a.start[cb + 1], 0.0f, me.x, 0.0f, me.y, true);
         } else {
             const int reach = E.reach;
             const int cx = cell_of(me.x, E.inv_cell, ncell);
             const int cy = cell_of(me.y, E.inv_cell, ncell);
             const int lo = cy - reach, hi = cy + reach;
-            for (int ox = -reach; ox <= reach; ++ox) {
-                int ccx = cx + ox;
-                float offx = 0.0f, xi = me.x;
-                if (ccx < 0) {
-                    ccx += ncell;
-                    offx = -L;
-                } else if (ccx >= ncell) {
-                    ccx -= ncell;
-                    xi = me.x - L;
-                }
-                const int colb = cb + ccx * ncell;
+            // the column's runs; a column left of cell 0 wraps to the right
+            // edge with its candidates shifted by -L (sx), one right of the
+            // last wraps to the left edge with the centre shifted instead
+            auto column = [&](auto sx, int colb, float offx, float xi) {
                 if (lo < 0) {
-                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo + ncell], a.start[colb + ncell],
-                                           li, pos, offx, xi, -L, me.y, false, L, r2, c2, K, nb, col);
-                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb], a.start[colb + hi + 1], li, pos, offx,
-                                           xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                    run(sx, Yes{}, a.start[colb + lo + ncell], a.start[colb + ncell], offx, xi, -L,
+                        me.y, false);
+                    run(sx, No{}, a.start[colb], a.start[colb + hi + 1], offx, xi, 0.0f, me.y, false);
                 } else if (hi >= ncell) {
-                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo], a.start[colb + ncell], li, pos,
-                                           offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
-                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb], a.start[colb + hi - ncell + 1],
-                                           li, pos, offx, xi, 0.0f, me.y - L, false, L, r2, c2, K, nb, col);
+                    run(sx, No{}, a.start[colb + lo], a.start[colb + ncell], offx, xi, 0.0f, me.y,
+                        false);
+                    run(sx, No{}, a.start[colb], a.start[colb + hi - ncell + 1], offx, xi, 0.0f,
+                        me.y - L, false);
                 } else {
-                    sweep_run<A, G, kUnroll, kFov, kTag>(smin, a.sxy, a.stype, ti, a.start[colb + lo], a.start[colb + hi + 1], li, pos,
-                                           offx, xi, 0.0f, me.y, false, L, r2, c2, K, nb, col);
+                    run(sx, No{}, a.start[colb + lo], a.start[colb + hi + 1], offx, xi, 0.0f, me.y,
+                        false);
                 }
+            };
+            for (int ox = -reach; ox <= reach; ++ox) {
+                const int ccx = cx + ox;
+                if (ccx < 0) column(Yes{}, cb + (ccx + ncell) * ncell, -L, me.x);
+                else if (ccx >= ncell) column(No{}, cb + (ccx - ncell) * ncell, 0.0f, me.x - L);
+                else column(No{}, cb + ccx * ncell, 0.0f, me.x);
             }
         }
     }  // active
@@ -674,10 +724,12 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) /
 
 }  // namespace
 
-int scan_blocks_for(int64_t C) { return C <= kScanTile ? 0 : (int)((C + kTile2 - 1) / kTile2); }
+int scan_blocks_for(int64_t C, int64_t max_env_cells) {
+    return max_env_cells <= kScanTile ? 0 : (int)((C + kTile2 - 1) / kTile2);
+}
 
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
-    const int nb = scan_blocks_for(C);
+    const int64_t nb = (C + kTile2 - 1) / kTile2;  // partials of the two-level scan
     a->key = cv.take<int32_t>(G);
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
@@ -700,13 +752,13 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
 }
 
 namespace {
-template <int NT, int G, bool kFov, bool kTag>
+template <int NT, int G, bool kFov, bool kTag, int kM = 0>
 void launch_sweep_v(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
                     int add_return, hipStream_t s) {
     constexpr int A = NT / G;
     const size_t lds = (size_t)(kTag ? 2 : 1) * p.v * A * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag>), dim3(blocks_for(Gtot, A)), dim3(NT), lds, s,
-                       p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return);
+    hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag, kM>), dim3(blocks_for(Gtot, A)), dim3(NT), lds,
+                       s, p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return);
 }
 
 template <int NT, int G>
@@ -715,9 +767,16 @@ void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, f
     if (p.tag) {
         if (p.fov) launch_sweep_v<NT, G, true, true>(p, envs, Gtot, obs, reward, add_return, s);
         else launch_sweep_v<NT, G, false, true>(p, envs, Gtot, obs, reward, add_return, s);
+    } else if (p.fov) {
+        launch_sweep_v<NT, G, true, false>(p, envs, Gtot, obs, reward, add_return, s);
+    } else if (p.v == 8) {
+        launch_sweep_v<NT, G, false, false, 1>(p, envs, Gtot, obs, reward, add_return, s);
+    } else if (p.v == 16) {
+        launch_sweep_v<NT, G, false, false, 2>(p, envs, Gtot, obs, reward, add_return, s);
+    } else if (p.v == 32) {
+        launch_sweep_v<NT, G, false, false, 4>(p, envs, Gtot, obs, reward, add_return, s);
     } else {
-        if (p.fov) launch_sweep_v<NT, G, true, false>(p, envs, Gtot, obs, reward, add_return, s);
-        else launch_sweep_v<NT, G, false, false>(p, envs, Gtot, obs, reward, add_return, s);
+        launch_sweep_v<NT, G, false, false>(p, envs, Gtot, obs, reward, add_return, s);
     }
 }
 }  // namespace
@@ -733,7 +792,8 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
                        reinterpret_cast<const float2 *>(act));
     if (ev) (void)hipEventRecord(ev[1], s);
     if (p.scan_blocks == 0) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanNT), 0, s, p.a.count, p.a.start, C);
+        hipLaunchKernelGGL(k_scan_env, dim3(p.n_envs), dim3(kScanNT), 0, s, p.a.count, p.a.start,
+                           envs, p.n_envs, C);
     } else {
         hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
                            p.a.part, p.a.ticket, p.a.start, C);

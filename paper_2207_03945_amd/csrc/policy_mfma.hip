@@ -107,7 +107,11 @@ struct OutArgs {
 // is non-null, each row's env-owned rows found through the batch tables.
 // kLdsW1: the layer-1 A operand (kc1 > kRegChunks chunks of 16 inputs) is
 // staged in dynamic LDS once per block instead of living in registers.
-template <bool kLdsW1, int kOut>
+// kStage (batch-wide obs rows): each wave copies its tile's 32 consecutive
+// rows, one contiguous block of 32 in_dim floats, into LDS with coalesced
+// 16-byte loads (rounded to BF16 on the way), and the MFMA operands are read
+// from there; otherwise every lane loads its own row.
+template <bool kLdsW1, int kOut, bool kStage>
 __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
                                                       float max_turn, float max_dspeed,
                                                       const float *__restrict__ obs, int64_t n,
@@ -116,7 +120,12 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                                                       const int32_t *__restrict__ base, int n_envs,
                                                       OutArgs oa) {
     __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
-    extern __shared__ bf16x8 s_w1[];  // [kc1][2 tiles][64 lanes] when kLdsW1
+    extern __shared__ bf16x8 s_dyn[];
+    bf16x8 *s_w1 = s_dyn;  // [kc1][2 tiles][64 lanes] when kLdsW1
+    // per-wave obs tiles after the weights: [32 rows][ld] BF16, ld = 16 kc1 + 8
+    const int ld = 16 * kc1 + 8;
+    __bf16 *s_obs = reinterpret_cast<__bf16 *>(s_dyn + (kLdsW1 ? kc1 * 128 : 0)) +
+                    (size_t)(threadIdx.x / 64) * 32 * ld;
     if (kLdsW1)
         for (int i = threadIdx.x; i < kc1 * 128; i += kPolBlock) s_w1[i] = P.w1f[i];
     for (int i = threadIdx.x; i < 64; i += kPolBlock) {
@@ -154,6 +163,31 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
         }
         const float *orow = obs + agent * in_dim;
         float2 *arow = act + agent;
+        if constexpr (kStage) {
+            const int64_t row0 = tile * 32;
+            const int rows = n - row0 < 32 ? (int)(n - row0) : 32;
+            const float *src = obs + row0 * in_dim;
+            const int cnt = rows * in_dim, cnt4 = cnt >> 2;
+            __threadfence_block();  // the previous tile's reads come first
+            for (int e4 = lane; e4 < cnt4; e4 += 64) {
+                const float4 q = reinterpret_cast<const float4 *>(src)[e4];
+                int r = (4 * e4) / in_dim, k = 4 * e4 - r * in_dim;
+                const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    s_obs[r * ld + k] = (__bf16)qv[u];
+                    if (++k == in_dim) {
+                        k = 0;
+                        ++r;
+                    }
+                }
+            }
+            for (int e = 4 * cnt4 + lane; e < cnt; e += 64) {
+                const int r = e / in_dim;
+                s_obs[r * ld + (e - r * in_dim)] = (__bf16)src[e];
+            }
+            __threadfence_block();  // this wave's copies before its reads
+        }
         if (envs && valid) {
             const DevEnv &E = envs[env_of_row(base, n_envs, agent)];
             const int64_t i = agent - E.agent_base;
@@ -164,7 +198,12 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
         for (int kc = 0; kc < kc1; ++kc) {
             bf16x8 xb;
             const int k0 = 16 * kc + 8 * g;
-            if (valid && in_dim % 4 == 0 && k0 + 8 <= in_dim) {
+            if constexpr (kStage) {
+                xb = *reinterpret_cast<const bf16x8 *>(s_obs + col * ld + k0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (!valid || k0 + j >= in_dim) xb[j] = (__bf16)0.0f;
+            } else if (valid && in_dim % 4 == 0 && k0 + 8 <= in_dim) {
                 const float4 *src = reinterpret_cast<const float4 *>(orow + k0);
                 const float4 u = src[0], w = src[1];
                 xb[0] = (__bf16)u.x; xb[1] = (__bf16)u.y; xb[2] = (__bf16)u.z; xb[3] = (__bf16)u.w;
@@ -276,14 +315,25 @@ hipError_t launch_pol(const pol_t *p, const float *obs, int64_t n, float *act, c
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 4096) blocks = 4096;
     float2 *a2 = reinterpret_cast<float2 *>(act);
-    if (p->kc1 > kRegChunks)
-        hipLaunchKernelGGL((k_policy<true, kOut>), dim3((unsigned)blocks), dim3(kPolBlock),
-                           w1_lds_bytes(p->kc1), s, p->lay, p->in_dim, p->kc1, p->max_turn,
-                           p->max_dspeed, obs, n, a2, envs, base, n_envs, oa);
-    else
-        hipLaunchKernelGGL((k_policy<false, kOut>), dim3((unsigned)blocks), dim3(kPolBlock), 0, s,
-                           p->lay, p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n, a2, envs,
-                           base, n_envs, oa);
+    // batch-wide rows whose tiles start 16-byte aligned are staged through LDS
+    // (within the 64 KiB of dynamic LDS a launch gets by default)
+    const size_t w1b = p->kc1 > kRegChunks ? w1_lds_bytes(p->kc1) : 0;
+    const size_t tile_b = (size_t)(kPolBlock / 64) * 32 * (16 * p->kc1 + 8) * sizeof(__bf16);
+    const bool stage = obs && !envs && (reinterpret_cast<uintptr_t>(obs) & 15) == 0 &&
+                       w1b + tile_b <= 65536;
+    const size_t obs_b = stage ? tile_b : 0;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kPolBlock), w1b + obs_b, s, p->lay,
+                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n, a2, envs, base,
+                           n_envs, oa);
+    };
+    if (p->kc1 > kRegChunks) {
+        if (stage) go(k_policy<true, kOut, true>);
+        else go(k_policy<true, kOut, false>);
+    } else {
+        if (stage) go(k_policy<false, kOut, true>);
+        else go(k_policy<false, kOut, false>);
+    }
     return hipGetLastError();
 }
 }  // namespace

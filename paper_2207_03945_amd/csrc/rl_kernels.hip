@@ -22,7 +22,7 @@ namespace flock {
 namespace {
 
 constexpr int kGaeBlock = 256;
-constexpr int kChunk = 8;
+constexpr int kChunk = 16;
 
 __global__ __launch_bounds__(kGaeBlock) void k_gae(int T, int64_t n, double gamma, double gl,
                                                    const float *__restrict__ rew,

@@ -17,6 +17,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <vector>
@@ -244,7 +245,9 @@ int rebuild_plan(srv_t *S) {
         cand += env_candidates_per_agent(r.env) * r.p.n_agents;
     }
     S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v);
-    S->plan.scan_blocks = scan_blocks_for(c);
+    int64_t max_cells = 0;
+    for (int64_t rid : S->running) max_cells = std::max(max_cells, env_cell_count(S->reqs.at(rid).env));
+    S->plan.scan_blocks = scan_blocks_for(c, max_cells);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)
         e = hipMemcpyAsync(S->plan.a.envs[f], S->tab[f].data(), S->tab[f].size() * sizeof(DevEnv),

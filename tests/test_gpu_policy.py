@@ -106,3 +106,21 @@ def test_step_policy_equals_forward_then_step():
         assert torch.equal(act_a, act_b), t
         assert torch.equal(obs_a, obs_b), t
         assert torch.equal(rew_a, rew_b), t
+
+
+@pytest.mark.parametrize("in_dim", [16, 129, 20])
+def test_policy_staged_and_direct_loads_agree_bitwise(in_dim):
+    """Rows staged through LDS (16-byte aligned obs) and rows loaded per lane
+    (obs starting 4 bytes in) give the same actions."""
+    pol, _, _ = make_policy(in_dim)
+    n = 1000
+    g = np.random.default_rng(in_dim)
+    obs = torch.from_numpy(g.random((n, in_dim)).astype(np.float32)).cuda()
+    big = torch.empty(n * in_dim + 1, device="cuda")
+    shifted = big[1:].view(n, in_dim)
+    shifted.copy_(obs)
+    assert shifted.data_ptr() % 16 != 0
+    a = pol.forward(obs)
+    b = pol.forward(shifted)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

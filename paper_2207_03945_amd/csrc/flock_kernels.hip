@@ -488,6 +488,42 @@ struct ViewK {
 // touches with the other type (the lane's own type is ti).
 // kShiftX / kShiftY: the candidate-side shift offx / offy may be nonzero (a
 // zero shift is left out: x + 0 = x for the nonnegative coordinates here).
+template <int S, bool kFov, bool kTag, int kM, bool kShiftX, bool kShiftY>
+__device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__restrict__ stype,
+                                          int ti, const float2 pj, int qq, int self, float offx,
+                                          float xi, float offy, float yi, bool minimg, float L,
+                                          float r2, float c2, const ViewK &K, int &nb, int &col) {
+    float dx, dy;
+    if (minimg) {
+        dx = min_image_delta(pj.x, xi, L);
+        dy = min_image_delta(pj.y, yi, L);
+    } else {
+        dx = (kShiftX ? pj.x + offx : pj.x) - xi;
+        dy = (kShiftY ? pj.y + offy : pj.y) - yi;
+    }
+    const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+    const bool nbr = d2 < r2 && qq != self;
+    int ch = 0;  // view channel offset (sectors)
+    if constexpr (kTag) {
+        const int tj = stype[qq];
+        nb += (nbr && tj == 0) ? 1 : 0;
+        col += (nbr && tj != ti && d2 < c2) ? 1 : 0;
+        ch = tj * K.v;
+    } else {
+        nb += nbr ? 1 : 0;
+        col += (nbr && d2 < c2) ? 1 : 0;
+    }
+    if (kFov) {
+        const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
+        if (nbr && k >= 0) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
+    } else {
+        int k;
+        if constexpr (kM > 0) k = sector_oct<kM>(dx, dy, K.c, K.s);
+        else k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
+        if (nbr) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
+    }
+}
+
 template <int S, int G, int UNROLL, bool kFov, bool kTag, int kM, bool kShiftX, bool kShiftY>
 __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__restrict__ sxy,
                                           const uint8_t *__restrict__ stype, int ti,
@@ -495,35 +531,8 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
                                           float offy, float yi, bool minimg, float L, float r2,
                                           float c2, const ViewK &K, int &nb, int &col) {
     auto test = [&](const float2 pj, int qq) {
-        float dx, dy;
-        if (minimg) {
-            dx = min_image_delta(pj.x, xi, L);
-            dy = min_image_delta(pj.y, yi, L);
-        } else {
-            dx = (kShiftX ? pj.x + offx : pj.x) - xi;
-            dy = (kShiftY ? pj.y + offy : pj.y) - yi;
-        }
-        const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-        const bool nbr = d2 < r2 && qq != self;
-        int ch = 0;  // view channel offset (sectors)
-        if constexpr (kTag) {
-            const int tj = stype[qq];
-            nb += (nbr && tj == 0) ? 1 : 0;
-            col += (nbr && tj != ti && d2 < c2) ? 1 : 0;
-            ch = tj * K.v;
-        } else {
-            nb += nbr ? 1 : 0;
-            col += (nbr && d2 < c2) ? 1 : 0;
-        }
-        if (kFov) {
-            const int k = view_sector(dx, dy, K.c, K.s, K.fov_half, K.fov_t, K.sec_scale, K.v);
-            if (nbr && k >= 0) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
-        } else {
-            int k;
-            if constexpr (kM > 0) k = sector_oct<kM>(dx, dy, K.c, K.s);
-            else k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
-            if (nbr) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
-        }
+        test_pair<S, kFov, kTag, kM, kShiftX, kShiftY>(smin_own, stype, ti, pj, qq, self, offx, xi,
+                                                       offy, yi, minimg, L, r2, c2, K, nb, col);
     };
     q += li;
     for (; q + (UNROLL - 1) * G < q1; q += UNROLL * G) {
@@ -538,6 +547,12 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
 
 // Candidates per loop iteration of the sweep (independent loads in flight).
 constexpr int kUnroll = 4;
+// One lane per agent: walk the block's runs as one sequence (a lane moves to
+// its next run as soon as its current one ends) instead of run by run, so a
+// wave waits for its longest total rather than for the longest lane of every
+// run (on MI355X: 96 -> 83 us for 1M agents at 30 candidates each).
+constexpr bool kFlatRuns = true;
+constexpr int kFlatUnroll = 2;  // candidates per step while a run has that many left
 
 // NT threads per block, G lanes per agent (in the new cell order): A = NT/G
 // agents per block, their sector minima v * A * 4 bytes of dynamic LDS.  G = 1
@@ -622,11 +637,85 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                         false);
                 }
             };
-            for (int ox = -reach; ox <= reach; ++ox) {
-                const int ccx = cx + ox;
-                if (ccx < 0) column(Yes{}, cb + (ccx + ncell) * ncell, -L, me.x);
-                else if (ccx >= ncell) column(No{}, cb + (ccx - ncell) * ncell, 0.0f, me.x - L);
-                else column(No{}, cb + ccx * ncell, 0.0f, me.x);
+            if constexpr (G == 1 && kFlatRuns) {
+                // run state: column oxi of 2 reach + 1, segment seg of the column
+                int oxi = 0, seg = 0, q = 0, q1 = 0;
+                float offx = 0.0f, xi = me.x, offy = 0.0f, yi = me.y;
+                auto next_run = [&]() -> bool {
+                    while (oxi <= 2 * reach) {
+                        int ccx = cx - reach + oxi;
+                        offx = 0.0f;
+                        xi = me.x;
+                        if (ccx < 0) {
+                            ccx += ncell;
+                            offx = -L;
+                        } else if (ccx >= ncell) {
+                            ccx -= ncell;
+                            xi = me.x - L;
+                        }
+                        const int colb = cb + ccx * ncell;
+                        offy = 0.0f;
+                        yi = me.y;
+                        int nseg = 1;
+                        if (lo < 0) {
+                            nseg = 2;
+                            if (seg == 0) {
+                                q = a.start[colb + lo + ncell];
+                                q1 = a.start[colb + ncell];
+                                offy = -L;
+                            } else {
+                                q = a.start[colb];
+                                q1 = a.start[colb + hi + 1];
+                            }
+                        } else if (hi >= ncell) {
+                            nseg = 2;
+                            if (seg == 0) {
+                                q = a.start[colb + lo];
+                                q1 = a.start[colb + ncell];
+                            } else {
+                                q = a.start[colb];
+                                q1 = a.start[colb + hi - ncell + 1];
+                                yi = me.y - L;
+                            }
+                        } else {
+                            q = a.start[colb + lo];
+                            q1 = a.start[colb + hi + 1];
+                        }
+                        if (++seg >= nseg) {
+                            seg = 0;
+                            ++oxi;
+                        }
+                        if (q < q1) return true;
+                    }
+                    return false;
+                };
+                bool more = next_run();
+                while (more) {
+                    if (q + kFlatUnroll <= q1) {
+                        float2 pj[kFlatUnroll];
+#pragma unroll
+                        for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
+#pragma unroll
+                        for (int u = 0; u < kFlatUnroll; ++u)
+                            test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, pj[u], q + u,
+                                                                     pos, offx, xi, offy, yi, false,
+                                                                     L, r2, c2, K, nb, col);
+                        q += kFlatUnroll;
+                    } else {
+                        test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, a.sxy[q], q,
+                                                                 pos, offx, xi, offy, yi, false, L,
+                                                                 r2, c2, K, nb, col);
+                        ++q;
+                    }
+                    if (q >= q1) more = next_run();
+                }
+            } else {
+                for (int ox = -reach; ox <= reach; ++ox) {
+                    const int ccx = cx + ox;
+                    if (ccx < 0) column(Yes{}, cb + (ccx + ncell) * ncell, -L, me.x);
+                    else if (ccx >= ncell) column(No{}, cb + (ccx - ncell) * ncell, 0.0f, me.x - L);
+                    else column(No{}, cb + ccx * ncell, 0.0f, me.x);
+                }
             }
         }
     }  // active

@@ -406,6 +406,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.fov = full_view(*p) ? 0 : 1;
     e->plan.tag = (p->flags & ENV_FLAG_TAG) ? 1 : 0;
     e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors);
+    e->plan.max_env_cells = e->plan.C;
     e->plan.scan_blocks = scan_blocks_for(e->plan.C, e->plan.C);
     *out = e;
     g_err.clear();
@@ -590,6 +591,7 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.lanes = batch_auto_lanes(b->envs);
     int64_t max_cells = 0;
     for (const env_t *e : b->envs) max_cells = std::max(max_cells, env_cell_count(e));
+    b->plan.max_env_cells = max_cells;
     b->plan.scan_blocks = scan_blocks_for(C, max_cells);
     *out = b;
     return ENV_OK;

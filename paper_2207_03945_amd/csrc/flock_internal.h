@@ -81,6 +81,7 @@ struct StepPlan {
     int lanes;    // lanes per agent in the sweep: 1, 4, 16 or 64
     int tag;      // the plan's envs are tag envs (two view channels)
     int scan_blocks;  // 0 -> one scan block per env (every env <= 16384 cells)
+    int64_t max_env_cells;  // cells of the plan's largest env
 };
 
 // Workspace carving --------------------------------------------------------

@@ -207,40 +207,41 @@ constexpr int kScanTile = kScanNT * kScanItems;  // cells of the single-block sc
 // + n), so its cell starts are agent_base plus the prefix within the env;
 // no block waits for another.  Re-zeroes the counts; the last env's block
 // also writes start[C] (= the batch's agent total).
-__global__ __launch_bounds__(kScanNT) void k_scan_env(int32_t *__restrict__ count,
-                                                      int32_t *__restrict__ start,
-                                                      const DevEnv *__restrict__ envs, int n_envs,
-                                                      int C) {
-    __shared__ int s_wave[kScanNT / 64 + 1];
-    __shared__ int s_tile[kScanTile];
+// NT threads of ITEMS cells each cover the largest env of the launch.
+template <int NT, int ITEMS>
+__global__ __launch_bounds__(NT) void k_scan_env(int32_t *__restrict__ count,
+                                                 int32_t *__restrict__ start,
+                                                 const DevEnv *__restrict__ envs, int n_envs, int C) {
+    __shared__ int s_wave[NT / 64 + 1];
+    __shared__ int s_tile[NT * ITEMS];
     const int t = threadIdx.x;
     const DevEnv &E = envs[blockIdx.x];
     const int cb = E.cell_base, Ce = E.ncell * E.ncell, base = E.agent_base;
     count += cb;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int idx = k * kScanNT + t;  // coalesced: item-major
+    for (int k = 0; k < ITEMS; ++k) {
+        const int idx = k * NT + t;  // coalesced: item-major
         s_tile[idx] = idx < Ce ? count[idx] : 0;
     }
     __syncthreads();
-    int vals[kScanItems];
+    int vals[ITEMS];
     int sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        vals[k] = s_tile[t * kScanItems + k];
+    for (int k = 0; k < ITEMS; ++k) {
+        vals[k] = s_tile[t * ITEMS + k];
         sum += vals[k];
     }
     int total;
-    int run = block_exclusive_scan<kScanNT>(sum, s_wave, &total) + base;
+    int run = block_exclusive_scan<NT>(sum, s_wave, &total) + base;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        s_tile[t * kScanItems + k] = run;
+    for (int k = 0; k < ITEMS; ++k) {
+        s_tile[t * ITEMS + k] = run;
         run += vals[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int idx = k * kScanNT + t;
+    for (int k = 0; k < ITEMS; ++k) {
+        const int idx = k * NT + t;
         if (idx < Ce) {
             start[cb + idx] = s_tile[idx];
             count[idx] = 0;
@@ -881,8 +882,12 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
                        reinterpret_cast<const float2 *>(act));
     if (ev) (void)hipEventRecord(ev[1], s);
     if (p.scan_blocks == 0) {
-        hipLaunchKernelGGL(k_scan_env, dim3(p.n_envs), dim3(kScanNT), 0, s, p.a.count, p.a.start,
-                           envs, p.n_envs, C);
+        if (p.max_env_cells <= 2048)
+            hipLaunchKernelGGL((k_scan_env<256, 8>), dim3(p.n_envs), dim3(256), 0, s, p.a.count,
+                               p.a.start, envs, p.n_envs, C);
+        else
+            hipLaunchKernelGGL((k_scan_env<kScanNT, kScanItems>), dim3(p.n_envs), dim3(kScanNT), 0, s,
+                               p.a.count, p.a.start, envs, p.n_envs, C);
     } else {
         hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
                            p.a.part, p.a.ticket, p.a.start, C);

@@ -247,6 +247,7 @@ int rebuild_plan(srv_t *S) {
     S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v);
     int64_t max_cells = 0;
     for (int64_t rid : S->running) max_cells = std::max(max_cells, env_cell_count(S->reqs.at(rid).env));
+    S->plan.max_env_cells = max_cells;
     S->plan.scan_blocks = scan_blocks_for(c, max_cells);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)

@@ -409,7 +409,7 @@ __device__ __forceinline__ int sector_of(float dx, float dy, float c, float s, f
 
 // As sector_of for a full view with v = 8 M sectors (M sectors per octant),
 // without the arctangent: the octant comes from the signs and the larger of
-// |u| and |w|, the sector within it from comparing t = min/max with the
+// |u| and |w|, the sector within it from comparing min/max with the
 // tangents of the octant's interior sector edges, and mirrored octants
 // count their sectors backwards.  A bearing exactly on an octant edge may
 // land in either neighbouring sector (both are within the ambiguity band).
@@ -418,16 +418,17 @@ __device__ __forceinline__ int sector_oct(float dx, float dy, float c, float s) 
     const float u = __builtin_fmaf(dx, c, dy * s);
     const float w = __builtin_fmaf(dy, c, -(dx * s));
     const float au = fabsf(u), aw = fabsf(w);
+    // min/max > tan(edge), tested as min > tan(edge) * max (no division; a
+    // coincident pair, max = 0, stays in sector 0)
     int j = 0;
     if constexpr (M > 1) {
         const float mx = fmaxf(au, aw), mn = fminf(au, aw);
-        const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
         if constexpr (M == 2) {
-            j = t >= 0.41421356237309503f ? 1 : 0;  // tan(pi/8)
+            j = mn > 0.41421356237309503f * mx ? 1 : 0;  // tan(pi/8)
         } else {
             static_assert(M == 4, "sector_oct takes M = 1, 2 or 4");
-            j = (t >= 0.19891236737965800f ? 1 : 0) + (t >= 0.41421356237309503f ? 1 : 0) +
-                (t >= 0.66817863791929891f ? 1 : 0);  // tan(pi/16), tan(pi/8), tan(3 pi/16)
+            j = (mn > 0.19891236737965800f * mx ? 1 : 0) + (mn > 0.41421356237309503f * mx ? 1 : 0) +
+                (mn > 0.66817863791929891f * mx ? 1 : 0);  // tan(pi/16), tan(pi/8), tan(3 pi/16)
         }
     }
     int k = aw > au ? 2 * M - 1 - j : j;

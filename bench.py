@@ -256,6 +256,8 @@ def bench_rollout(flock, workloads, reps=3):
     assert torch.isfinite(adv).all() and torch.isfinite(val).all()
     t = np.median(np.asarray(times), axis=0)
     gae_bytes = 16 * T * n
+    # critic FLOPs over the (T + 1) n views: in x 64 + 64 x 64 + 64 x 1 MACs per row
+    critic_flop = 2 * (T + 1) * n * (d * 64 + 64 * 64 + 64)
     return {"workload": f"one env, {n:,} agents, the paper's flock settings (box 100, vision 10, "
                         f"128 sectors, 250 degrees, speed in the view), {T} sampled steps per "
                         "collection; critic over the 129 x N views; advantages",
@@ -263,6 +265,10 @@ def bench_rollout(flock, workloads, reps=3):
             "collect_ms": float(t.sum()), "agent_steps_per_s": n * T / (t[0] * 1e-3),
             "buffer_bytes": int((obs.numel() + act.numel() + logp.numel() + rew.numel()
                                  + val.numel() + adv.numel() + ret.numel()) * 4),
+            "critic_mfma": {"flop_per_launch": critic_flop,
+                            "achieved_TFLOPs": critic_flop / (t[1] * 1e-3) / 1e12,
+                            "peak_TFLOPs": 2500.0,
+                            "frac": critic_flop / (t[1] * 1e-3) / 2.5e15},
             "gae_hbm": {"bytes_per_launch": gae_bytes,
                         "achieved_GBps": gae_bytes / (t[2] * 1e-3) / 1e9,
                         "frac": gae_bytes / (t[2] * 1e-3) / HBM_PEAK}}

@@ -118,6 +118,14 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s);
 hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
                        float *reward, int add_return, hipStream_t s,
                        hipEvent_t *phase_events = nullptr);
+// The step's phases, in order.  Data they share: move writes tmp/key/slot and
+// the counts and reads the current records; scan turns counts into starts;
+// scatter writes the next records, sxy and stype; sweep reads those and the
+// starts.
+enum StepPhase { kPhaseMove = 0, kPhaseScan = 1, kPhaseScatter = 2, kPhaseSweep = 3 };
+hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_move,
+                        const float *act, float *obs, float *reward, int add_return,
+                        hipStream_t s);
 // Load an agent-order state into buffer `rec`/`id` (identity order).
 hipError_t launch_load_state(const float *x, const float *y, const float *th, const float *sp,
                              float4 *rec, int32_t *id, int n, hipStream_t s);

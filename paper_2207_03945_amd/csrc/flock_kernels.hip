@@ -872,40 +872,62 @@ void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, f
 }
 }  // namespace
 
-hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
-                       float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
+hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_move,
+                        const float *act, float *obs, float *reward, int add_return,
+                        hipStream_t s) {
     if (p.G == 0) return hipSuccess;
     const int G = (int)p.G, C = (int)p.C;
     const DevEnv *envs = p.a.envs[table & 1];
     const unsigned nb = blocks_for(G, kBlock);
-    if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G, do_move,
-                       reinterpret_cast<const float2 *>(act));
-    if (ev) (void)hipEventRecord(ev[1], s);
-    if (p.scan_blocks == 0) {
-        if (p.max_env_cells <= 2048)
-            hipLaunchKernelGGL((k_scan_env<256, 8>), dim3(p.n_envs), dim3(256), 0, s, p.a.count,
-                               p.a.start, envs, p.n_envs, C);
-        else
-            hipLaunchKernelGGL((k_scan_env<kScanNT, kScanItems>), dim3(p.n_envs), dim3(kScanNT), 0, s,
-                               p.a.count, p.a.start, envs, p.n_envs, C);
-    } else {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
-                           p.a.part, p.a.ticket, p.a.start, C);
-        hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScan2NT), 0, s, p.a.count,
-                           p.a.part, p.a.start, C);
+    switch (phase) {
+        case kPhaseMove:
+            hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G,
+                               do_move, reinterpret_cast<const float2 *>(act));
+            break;
+        case kPhaseScan:
+            if (p.scan_blocks == 0) {
+                if (p.max_env_cells <= 2048)
+                    hipLaunchKernelGGL((k_scan_env<256, 8>), dim3(p.n_envs), dim3(256), 0, s,
+                                       p.a.count, p.a.start, envs, p.n_envs, C);
+                else
+                    hipLaunchKernelGGL((k_scan_env<kScanNT, kScanItems>), dim3(p.n_envs),
+                                       dim3(kScanNT), 0, s, p.a.count, p.a.start, envs, p.n_envs, C);
+            } else {
+                hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s,
+                                   p.a.count, p.a.part, p.a.ticket, p.a.start, C);
+                hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScan2NT), 0, s,
+                                   p.a.count, p.a.part, p.a.start, C);
+            }
+            break;
+        case kPhaseScatter:
+            hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G,
+                               p.tag);
+            break;
+        case kPhaseSweep: {
+            const int lanes = p.lanes;
+            if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s);
+            else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s);
+            else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s);
+            else if ((p.tag ? 2 * p.v : p.v) <= 32)
+                launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
+            else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s);
+            break;
+        }
     }
-    if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G, p.tag);
-    if (ev) (void)hipEventRecord(ev[3], s);
-    const int lanes = p.lanes;
-    if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s);
-    else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s);
-    else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s);
-    else if ((p.tag ? 2 * p.v : p.v) <= 32) launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
-    else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s);
-    if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
+}
+
+hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
+                       float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
+    if (p.G == 0) return hipSuccess;
+    const StepPhase order[4] = {kPhaseMove, kPhaseScan, kPhaseScatter, kPhaseSweep};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        if (ev) (void)hipEventRecord(ev[k], s);
+        e = launch_phase(p, table, order[k], do_move, act, obs, reward, add_return, s);
+    }
+    if (ev) (void)hipEventRecord(ev[4], s);
+    return e;
 }
 
 hipError_t launch_load_state(const float *x, const float *y, const float *th, const float *sp,

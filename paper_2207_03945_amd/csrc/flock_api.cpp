@@ -407,6 +407,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.tag = (p->flags & ENV_FLAG_TAG) ? 1 : 0;
     e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors);
     e->plan.max_env_cells = e->plan.C;
+    e->plan.env_sort_recs = 0;  // one env: the multi-block kernels fill the GPU better
     e->plan.scan_blocks = scan_blocks_for(e->plan.C, e->plan.C);
     *out = e;
     g_err.clear();
@@ -589,9 +590,13 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.fov = fov;
     b->plan.tag = (envs[0]->p.flags & ENV_FLAG_TAG) ? 1 : 0;
     b->plan.lanes = batch_auto_lanes(b->envs);
-    int64_t max_cells = 0;
-    for (const env_t *e : b->envs) max_cells = std::max(max_cells, env_cell_count(e));
+    int64_t max_cells = 0, max_agents = 0;
+    for (const env_t *e : b->envs) {
+        max_cells = std::max(max_cells, env_cell_count(e));
+        max_agents = std::max(max_agents, (int64_t)e->p.n_agents);
+    }
     b->plan.max_env_cells = max_cells;
+    b->plan.env_sort_recs = env_sort_recs_for(n_envs, max_agents, max_cells);
     b->plan.scan_blocks = scan_blocks_for(C, max_cells);
     *out = b;
     return ENV_OK;

@@ -82,6 +82,7 @@ struct StepPlan {
     int tag;      // the plan's envs are tag envs (two view channels)
     int scan_blocks;  // 0 -> one scan block per env (every env <= 16384 cells)
     int64_t max_env_cells;  // cells of the plan's largest env
+    int env_sort_recs;      // > 0: one block per env does move to scatter (records per thread)
 };
 
 // Workspace carving --------------------------------------------------------
@@ -104,6 +105,9 @@ struct Carver {
 // Tiles of the two-level scan over C cells, or 0 when every env has few
 // enough cells (max_env_cells) for one scan block per env.
 int scan_blocks_for(int64_t C, int64_t max_env_cells);
+// Records per thread of the per-env fused sort for this plan shape, or 0 when
+// the envs are too few to fill the GPU or too large for one block.
+int env_sort_recs_for(int n_envs, int64_t max_env_agents, int64_t max_env_cells);
 // Carve the sort scratch for G agents, C cells and E envs.
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 

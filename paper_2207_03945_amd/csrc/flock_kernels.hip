@@ -68,6 +68,38 @@ __device__ __forceinline__ int env_search(const int32_t *base, int n_envs, int r
     return lo;
 }
 
+// The same search by the 64 lanes of one wave: each round splits [lo, hi)
+// into 64 strides and keeps the last stride whose first base is <= row
+// (base[lo] <= row holds throughout), so up to 64^k envs take k dependent
+// loads instead of log2 of them.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_env_search(const int32_t *base, int n_envs, int row) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n_envs;
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int e = lo + lane * step;
+        const bool ok = e < hi && base[e] <= row;
+        const uint64_t m = __ballot(ok);  // lane 0 (e = lo) is always set
+        lo += (63 - __builtin_clzll(m)) * step;
+        hi = hi < lo + step ? hi : lo + step;
+    }
+    return lo;
+}
+
+constexpr bool kWaveSearch = true;
+
+// Env of the block's first row into s_env (wave 0 searches).
+__device__ __forceinline__ void block_env(int *s_env, const int32_t *base, int n_envs, int row) {
+    if (kWaveSearch) {
+        if (threadIdx.x < 64) {
+            const int e = wave_env_search(base, n_envs, row);
+            if (threadIdx.x == 0) *s_env = e;
+        }
+    } else if (threadIdx.x == 0) {
+        *s_env = env_search(base, n_envs, row);
+    }
+}
+
 __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
@@ -84,59 +116,101 @@ __device__ __forceinline__ int wave_max(int x) {
 
 constexpr int kHistBins = 2048;
 
+// One agent's move (Sec. 4.1): turn, speed update (tag: the action is the
+// speed), integrate with the new heading and speed, wrap into [0, L).
+__device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 av) {
+    float x = r.x, y = r.y, h = r.z, sp = r.w;
+    const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
+    h = h + turn;
+    if (h < 0.0f) h = h + kTwoPiF;
+    if (h >= kTwoPiF) h = h - kTwoPiF;
+    if (E.tag) {
+        sp = fminf(fmaxf(av.y, 0.0f), E.s_max);
+    } else {
+        const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
+        sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
+    }
+    double sd, cd;
+    sincos((double)h, &sd, &cd);
+    const float c = (float)cd, sn = (float)sd;
+    const float L = E.box;
+    float nx = x + sp * c;
+    if (nx < 0.0f) nx = nx + L;
+    if (nx >= L) nx = nx - L;
+    float ny = y + sp * sn;
+    if (ny < 0.0f) ny = ny + L;
+    if (ny >= L) ny = ny - L;
+    return make_float4(nx, ny, h, sp);
+}
+
+// Cell of a position within its env's grid.
+__device__ __forceinline__ int local_cell(const DevEnv &E, float x, float y) {
+    return cell_of(x, E.inv_cell, E.ncell) * E.ncell + cell_of(y, E.inv_cell, E.ncell);
+}
+
+// Records per thread of the move kernel: a block covers kMoveRecs * kBlock
+// consecutive records, all of whose loads are issued before any compute.
+constexpr int kMoveRecs = 1;
+
 __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEnv *__restrict__ envs,
                                                        int n_envs, int G, int do_move,
                                                        const float2 *__restrict__ act) {
+    constexpr int R = kMoveRecs;
     __shared__ int s_env;
     __shared__ int s_kmin[kBlock / 64], s_kmax[kBlock / 64];
     __shared__ int s_hist[kHistBins];
-    const int p0 = blockIdx.x * kBlock;
-    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    const int p0 = blockIdx.x * (kBlock * R);
+    block_env(&s_env, a.base, n_envs, p0);
     __syncthreads();
-    const int p = p0 + threadIdx.x;
-    const bool live = p < G;
-    int key = 0;
-    if (live) {
-        int e = s_env;
-        while (a.base[e + 1] <= p) ++e;
-        const DevEnv &E = envs[e];
-        const int i = p - E.agent_base;
-        const float4 r = E.rec_cur[i];
-        float x = r.x, y = r.y, h = r.z, sp = r.w;
-        if (do_move) {
-            const int id = E.id_cur[i];
-            const float2 av =
-                act ? act[E.agent_base + id] : reinterpret_cast<const float2 *>(E.act)[id];
-            const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
-            h = h + turn;
-            if (h < 0.0f) h = h + kTwoPiF;
-            if (h >= kTwoPiF) h = h - kTwoPiF;
-            if (E.tag) {
-                sp = fminf(fmaxf(av.y, 0.0f), E.s_max);  // tag: the action is the speed
-            } else {
-                const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
-                sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
-            }
-            double sd, cd;
-            sincos((double)h, &sd, &cd);
-            const float c = (float)cd, sn = (float)sd;
-            const float L = E.box;
-            float nx = x + sp * c;
-            if (nx < 0.0f) nx = nx + L;
-            if (nx >= L) nx = nx - L;
-            float ny = y + sp * sn;
-            if (ny < 0.0f) ny = ny + L;
-            if (ny >= L) ny = ny - L;
-            x = nx;
-            y = ny;
+    // loads first: records, ids, then the actions they index
+    int env[R], key[R];
+    bool live[R];
+    float4 rec[R];
+    int id[R];
+    float2 av[R];
+    int e = s_env;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = p0 + r * kBlock + threadIdx.x;
+        live[r] = p < G;
+        key[r] = 0;
+        env[r] = e;
+        if (live[r]) {
+            while (a.base[e + 1] <= p) ++e;
+            env[r] = e;
+            const DevEnv &E = envs[e];
+            const int i = p - E.agent_base;
+            rec[r] = E.rec_cur[i];
+            id[r] = do_move ? E.id_cur[i] : 0;
         }
-        a.tmp[p] = make_float4(x, y, h, sp);
-        key = E.cell_base + cell_of(x, E.inv_cell, E.ncell) * E.ncell + cell_of(y, E.inv_cell, E.ncell);
-        a.key[p] = key;
+    }
+    if (do_move) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!live[r]) continue;
+            const DevEnv &E = envs[env[r]];
+            av[r] = act ? act[E.agent_base + id[r]] : reinterpret_cast<const float2 *>(E.act)[id[r]];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!live[r]) continue;
+        const int p = p0 + r * kBlock + threadIdx.x;
+        const DevEnv &E = envs[env[r]];
+        const float4 m = do_move ? move_record(E, rec[r], av[r]) : rec[r];
+        a.tmp[p] = m;
+        key[r] = E.cell_base + local_cell(E, m.x, m.y);
+        a.key[p] = key[r];
     }
     // key range of the block
-    int kmin = wave_min(live ? key : INT_MAX);
-    int kmax = wave_max(live ? key : INT_MIN);
+    int kmin = INT_MAX, kmax = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        kmin = min(kmin, live[r] ? key[r] : INT_MAX);
+        kmax = max(kmax, live[r] ? key[r] : INT_MIN);
+    }
+    kmin = wave_min(kmin);
+    kmax = wave_max(kmax);
     const int wid = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_kmin[wid] = kmin;
@@ -149,22 +223,28 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
         kmax = max(kmax, s_kmax[w]);
     }
     const int range = kmax - kmin;  // >= 0: every block holds at least one record
-    int slot = 0;
+    int slot[R];
     if (range < kHistBins) {
         for (int b = threadIdx.x; b <= range; b += kBlock) s_hist[b] = 0;
         __syncthreads();
-        const int lrank = live ? atomicAdd(&s_hist[key - kmin], 1) : 0;
+        int lrank[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lrank[r] = live[r] ? atomicAdd(&s_hist[key[r] - kmin], 1) : 0;
         __syncthreads();
         for (int b = threadIdx.x; b <= range; b += kBlock) {
             const int c = s_hist[b];
             if (c) s_hist[b] = atomicAdd(&a.count[kmin + b], c);
         }
         __syncthreads();
-        slot = live ? s_hist[key - kmin] + lrank : 0;
-    } else if (live) {
-        slot = atomicAdd(&a.count[key], 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) slot[r] = live[r] ? s_hist[key[r] - kmin] + lrank[r] : 0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) slot[r] = live[r] ? atomicAdd(&a.count[key[r]], 1) : 0;
     }
-    if (live) a.slot[p] = slot;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (live[r]) a.slot[p0 + r * kBlock + threadIdx.x] = slot[r];
 }
 
 // --------------------------------------------------------------------- scan
@@ -350,13 +430,85 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ co
     }
 }
 
+// --------------------------------------------------- per-env fused sort
+
+// Batches of many envs that each fit one block: block e moves env e's
+// agents, counts them per cell in LDS, scans its own cells and scatters the
+// records into the new cell order -- the move, count, scan and scatter of
+// the separate kernels in one launch, with no global atomics.  Ranks within
+// a cell come from LDS atomics, so the order inside a cell varies from run
+// to run; every output is independent of that order.  Up to R records per
+// thread; the env's cell counts, then starts, live in dynamic LDS.
+constexpr int kEnvNT = 1024;
+
+template <int R>
+__global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv *__restrict__ envs,
+                                                     int n_envs, int C, int do_move,
+                                                     const float2 *__restrict__ act, int tag) {
+    extern __shared__ int s_cells[];  // [Ce] counts, then starts within the env
+    __shared__ int s_wave[kEnvNT / 64 + 1];
+    const int tid = threadIdx.x;
+    const DevEnv &E = envs[blockIdx.x];
+    const int n = E.n, base = E.agent_base, cb = E.cell_base, Ce = E.ncell * E.ncell;
+    for (int c = tid; c < Ce; c += kEnvNT) s_cells[c] = 0;
+    __syncthreads();
+    int key[R], rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kEnvNT + tid;
+        key[r] = 0;
+        rank[r] = 0;
+        if (i < n) {
+            float4 m = E.rec_cur[i];
+            if (do_move) {
+                const int id = E.id_cur[i];
+                const float2 av = act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+                m = move_record(E, m, av);
+            }
+            a.tmp[base + i] = m;
+            key[r] = local_cell(E, m.x, m.y);
+            rank[r] = atomicAdd(&s_cells[key[r]], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counts: thread t owns cells [t k, t k + k)
+    const int per = (Ce + kEnvNT - 1) / kEnvNT;
+    const int c0 = tid * per;
+    int sum = 0;
+    for (int c = c0; c < c0 + per && c < Ce; ++c) sum += s_cells[c];
+    int total;
+    int run = block_exclusive_scan<kEnvNT>(sum, s_wave, &total);
+    for (int c = c0; c < c0 + per && c < Ce; ++c) {
+        const int cnt = s_cells[c];
+        s_cells[c] = run;
+        a.start[cb + c] = base + run;
+        run += cnt;
+    }
+    if (tid == 0 && blockIdx.x == n_envs - 1) a.start[C] = base + n;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kEnvNT + tid;
+        if (i < n) {
+            const int j = s_cells[key[r]] + rank[r];
+            const float4 m = a.tmp[base + i];
+            const int id = E.id_cur[i];
+            E.rec_nxt[j] = m;
+            E.id_nxt[j] = id;
+            E.ret_nxt[j] = E.ret_cur[i];
+            a.sxy[base + j] = make_float2(m.x, m.y);
+            if (tag) a.stype[base + j] = id < E.n_chasers ? 1 : 0;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ scatter
 
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *__restrict__ envs,
                                                     int n_envs, int G, int tag) {
     __shared__ int s_env;
     const int p0 = blockIdx.x * kBlock;
-    if (threadIdx.x == 0) s_env = env_search(a.base, n_envs, p0);
+    block_env(&s_env, a.base, n_envs, p0);
     __syncthreads();
     const int p = p0 + threadIdx.x;
     if (p >= G) return;
@@ -575,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     __shared__ int s_env;
     const int tid = threadIdx.x, slot = tid / G, li = tid % G;
     const int p0 = blockIdx.x * A;
-    if (tid == 0) s_env = env_search(a.base, n_envs, p0);
+    block_env(&s_env, a.base, n_envs, p0);
     uint32_t *smin = s_min + slot;
     if constexpr (G > 1)
         for (int k = li; k < vs; k += G) smin[k * A] = kInfBits;
@@ -815,6 +967,13 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) /
 
 }  // namespace
 
+int env_sort_recs_for(int n_envs, int64_t max_env_agents, int64_t max_env_cells) {
+    if (n_envs < 64 || max_env_cells > 16384) return 0;
+    for (int r = 2; r <= 16; r *= 2)
+        if (max_env_agents <= (int64_t)r * kEnvNT) return r;
+    return 0;
+}
+
 int scan_blocks_for(int64_t C, int64_t max_env_cells) {
     return max_env_cells <= kScanTile ? 0 : (int)((C + kTile2 - 1) / kTile2);
 }
@@ -881,10 +1040,24 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
     const unsigned nb = blocks_for(G, kBlock);
     switch (phase) {
         case kPhaseMove:
-            hipLaunchKernelGGL(k_move_count, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G,
-                               do_move, reinterpret_cast<const float2 *>(act));
+            if (p.env_sort_recs > 0) {
+                const size_t lds = (size_t)p.max_env_cells * sizeof(int);
+                const float2 *a2 = reinterpret_cast<const float2 *>(act);
+                const dim3 grid(p.n_envs), block(kEnvNT);
+                switch (p.env_sort_recs) {
+                    case 2: hipLaunchKernelGGL(k_env_sort<2>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
+                    case 4: hipLaunchKernelGGL(k_env_sort<4>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
+                    case 8: hipLaunchKernelGGL(k_env_sort<8>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
+                    default: hipLaunchKernelGGL(k_env_sort<16>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
+                }
+                break;
+            }
+            hipLaunchKernelGGL(k_move_count, dim3(blocks_for(G, kBlock * kMoveRecs)), dim3(kBlock),
+                               0, s, p.a, envs, p.n_envs, G, do_move,
+                               reinterpret_cast<const float2 *>(act));
             break;
         case kPhaseScan:
+            if (p.env_sort_recs > 0) break;  // done inside k_env_sort
             if (p.scan_blocks == 0) {
                 if (p.max_env_cells <= 2048)
                     hipLaunchKernelGGL((k_scan_env<256, 8>), dim3(p.n_envs), dim3(256), 0, s,
@@ -900,6 +1073,7 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
             }
             break;
         case kPhaseScatter:
+            if (p.env_sort_recs > 0) break;  // done inside k_env_sort
             hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G,
                                p.tag);
             break;

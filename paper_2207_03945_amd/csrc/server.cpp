@@ -245,9 +245,13 @@ int rebuild_plan(srv_t *S) {
         cand += env_candidates_per_agent(r.env) * r.p.n_agents;
     }
     S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v);
-    int64_t max_cells = 0;
-    for (int64_t rid : S->running) max_cells = std::max(max_cells, env_cell_count(S->reqs.at(rid).env));
+    int64_t max_cells = 0, max_agents = 0;
+    for (int64_t rid : S->running) {
+        max_cells = std::max(max_cells, env_cell_count(S->reqs.at(rid).env));
+        max_agents = std::max(max_agents, (int64_t)S->reqs.at(rid).p.n_agents);
+    }
     S->plan.max_env_cells = max_cells;
+    S->plan.env_sort_recs = env_sort_recs_for((int)S->running.size(), max_agents, max_cells);
     S->plan.scan_blocks = scan_blocks_for(c, max_cells);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)

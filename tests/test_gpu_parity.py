@@ -314,6 +314,50 @@ def test_sweep_lane_groups_bitwise_equal_to_one_lane(lanes):
                label=f"lanes {lanes}")
 
 
+def test_per_env_fused_sort_batch_bitwise_and_oracle():
+    """100+ small envs take the one-block-per-env sort; results equal each env stepped alone.
+
+    Includes an empty env, single-cell envs, a reach-2 env, a tag-free mix of
+    sizes 1 .. 3,000 and a view with more sectors; 6 steps, then the oracle on
+    sampled agents of every tenth env.
+    """
+    ns, boxes, states = _uneven(100, 20, 3000, seed=33)
+    extra = [(0, 64.0, 0), (1, 64.0, 0), (150, 20.0, 0), (800, 100.0, 2), (2, 30.0, 0)]
+    sts = list(states) + [workloads.uniform_state(n, b, seed=6) for n, b, _ in extra]
+    bxs = [float(b) for b in boxes] + [b for _, b, _ in extra]
+    reaches = [0] * len(ns) + [r for _, _, r in extra]
+    plain = [make_env(st, b, 16, reach=r)[0] for st, b, r in zip(sts, bxs, reaches)]
+    fused = [make_env(st, b, 16, reach=r)[0] for st, b, r in zip(sts, bxs, reaches)]
+    batch = flock.Batch(fused)
+    G, off = batch.n, batch.offsets
+    obs_b = torch.empty(G, 16, device="cuda")
+    rew_b = torch.empty(G, device="cuda")
+    acts_all = []
+    for t in range(6):
+        acts = [workloads.random_actions(st[0].shape[0], seed=3, step=t, env=k)
+                for k, st in enumerate(sts)]
+        acts_all.append(acts)
+        batch.step(dev(np.concatenate(acts).reshape(G, 2)), obs_b, rew_b)
+        for k, env in enumerate(plain):
+            o, r = env.step(dev(acts[k]))
+            assert torch.equal(o, obs_b[off[k]:off[k + 1]]), f"obs env {k} step {t}"
+            assert torch.equal(r, rew_b[off[k]:off[k + 1]]), f"reward env {k} step {t}"
+    for ea, eb in zip(plain, fused):
+        assert torch.equal(ea.returns(), eb.returns())
+        assert all(torch.equal(u, w) for u, w in zip(ea.get_state(), eb.get_state()))
+    g = np.random.default_rng(4)
+    for k in range(0, len(sts), 10):
+        st = sts[k]
+        for t in range(6):
+            st = oracle.oracle_move(st, acts_all[t][k], bxs[k])
+        n = st[0].shape[0]
+        if n == 0:
+            continue
+        agents = np.sort(g.choice(n, size=min(20, n), replace=False)).astype(np.int32)
+        check_step(fused[k], st, bxs[k], 16, obs_b[off[k]:off[k + 1]], rew_b[off[k]:off[k + 1]],
+                   agents=agents, label=f"fused env {k}")
+
+
 def test_batched_uneven_256_envs_against_oracle():
     """256 envs, N_e log-uniform in [100, 20,000] at density 1/16: sampled agents per env."""
     ns, boxes, states = _uneven(256, 100, 20000, seed=0)
@@ -339,8 +383,9 @@ def test_batched_uneven_256_envs_against_oracle():
         check_sense(o, obs_h[rows], rew_h[rows], nb[agents], col[agents], label=f"env {k}")
 
 
-def test_graph_replay_matches_eager():
-    ns, boxes, states = _uneven(10, 50, 2000, seed=7)
+@pytest.mark.parametrize("n_envs", [10, 80])   # 80: the one-block-per-env sort
+def test_graph_replay_matches_eager(n_envs):
+    ns, boxes, states = _uneven(n_envs, 50, 2000, seed=7)
     envs_g = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
     envs_e = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
     bg, be = flock.Batch(envs_g), flock.Batch(envs_e)

@@ -462,7 +462,8 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
             float4 m = E.rec_cur[i];
             if (do_move) {
                 const int id = E.id_cur[i];
-                const float2 av = act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+                const float2 av =
+                    act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
                 m = move_record(E, m, av);
             }
             a.tmp[base + i] = m;
@@ -969,6 +970,8 @@ inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) /
 
 int env_sort_recs_for(int n_envs, int64_t max_env_agents, int64_t max_env_cells) {
     if (n_envs < 64 || max_env_cells > 16384) return 0;
+    // (envs up to 16,384 agents: a 20,000-agent env in a batch of smaller
+    // ones keeps its block busy long after the rest are done)
     for (int r = 2; r <= 16; r *= 2)
         if (max_env_agents <= (int64_t)r * kEnvNT) return r;
     return 0;

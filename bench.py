@@ -118,7 +118,8 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False):
     return {"agent_steps_per_s": G * K / el, "ms_per_step": 1e3 * el / K, "agents": G,
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "phase_ms": {"move_count": float(ph[0]), "scan": float(ph[1]),
-                         "scatter": float(ph[2]), "sweep": float(ph[3])}}
+                         "scatter": float(ph[2]), "sweep": float(ph[3])},
+            "fused_sort": bool(ph[1] == 0 and ph[2] == 0)}
 
 
 def bench_plain(env, n, K, W, seed, tag=False):

@@ -222,7 +222,9 @@ int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs,
 
 /* One env_step_batched whose four phases are bracketed by HIP events on
  * `stream`: phase_ms[0] move + cell count, [1] scan, [2] scatter, [3]
- * neighbour sweep (milliseconds).  Synchronises the stream.  For
+ * neighbour sweep (milliseconds).  Batches of many small envs sort each
+ * env in one kernel (move, count, scan and scatter together): phase_ms[0]
+ * is then that kernel and [1], [2] are 0.  Synchronises the stream.  For
  * profiling; results are the same as env_step_batched. */
 int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *reward,
                            void *stream, float *phase_ms);

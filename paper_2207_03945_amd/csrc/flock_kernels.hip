@@ -438,8 +438,11 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ co
 // the separate kernels in one launch, with no global atomics.  Ranks within
 // a cell come from LDS atomics, so the order inside a cell varies from run
 // to run; every output is independent of that order.  Up to R records per
-// thread; the env's cell counts, then starts, live in dynamic LDS.
+// thread; the env's cell counts, then starts, live in dynamic LDS.  Up to
+// kEnvRegR records per thread the moved records and ids wait in registers
+// for the scatter; above that they are staged in `tmp`.
 constexpr int kEnvNT = 1024;
+constexpr int kEnvRegR = 8;
 
 template <int R>
 __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv *__restrict__ envs,
@@ -452,7 +455,11 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     const int n = E.n, base = E.agent_base, cb = E.cell_base, Ce = E.ncell * E.ncell;
     for (int c = tid; c < Ce; c += kEnvNT) s_cells[c] = 0;
     __syncthreads();
+    constexpr bool kRegs = R <= kEnvRegR;
+    constexpr int RR = kRegs ? R : 1;
     int key[R], rank[R];
+    float4 mr[RR];
+    int idr[RR];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = r * kEnvNT + tid;
@@ -460,13 +467,18 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         rank[r] = 0;
         if (i < n) {
             float4 m = E.rec_cur[i];
+            const int id = E.id_cur[i];
             if (do_move) {
-                const int id = E.id_cur[i];
                 const float2 av =
                     act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
                 m = move_record(E, m, av);
             }
-            a.tmp[base + i] = m;
+            if constexpr (kRegs) {
+                mr[r] = m;
+                idr[r] = id;
+            } else {
+                a.tmp[base + i] = m;
+            }
             key[r] = local_cell(E, m.x, m.y);
             rank[r] = atomicAdd(&s_cells[key[r]], 1);
         }
@@ -492,8 +504,15 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         const int i = r * kEnvNT + tid;
         if (i < n) {
             const int j = s_cells[key[r]] + rank[r];
-            const float4 m = a.tmp[base + i];
-            const int id = E.id_cur[i];
+            float4 m;
+            int id;
+            if constexpr (kRegs) {
+                m = mr[r];
+                id = idr[r];
+            } else {
+                m = a.tmp[base + i];
+                id = E.id_cur[i];
+            }
             E.rec_nxt[j] = m;
             E.id_nxt[j] = id;
             E.ret_nxt[j] = E.ret_cur[i];

@@ -314,15 +314,20 @@ def test_sweep_lane_groups_bitwise_equal_to_one_lane(lanes):
                label=f"lanes {lanes}")
 
 
-def test_per_env_fused_sort_batch_bitwise_and_oracle():
+@pytest.mark.parametrize("big", [0, 5000, 12000])
+def test_per_env_fused_sort_batch_bitwise_and_oracle(big):
     """100+ small envs take the one-block-per-env sort; results equal each env stepped alone.
 
     Includes an empty env, single-cell envs, a reach-2 env, a tag-free mix of
     sizes 1 .. 3,000 and a view with more sectors; 6 steps, then the oracle on
-    sampled agents of every tenth env.
+    sampled agents of every tenth env.  The largest env sets the records per
+    thread: up to 4,096 agents 4, with a 5,000-agent env 8 (records held in
+    registers), with a 12,000-agent env 16 (records staged in memory).
     """
     ns, boxes, states = _uneven(100, 20, 3000, seed=33)
     extra = [(0, 64.0, 0), (1, 64.0, 0), (150, 20.0, 0), (800, 100.0, 2), (2, 30.0, 0)]
+    if big:
+        extra.append((big, float(np.sqrt(big * 16.0)), 0))
     sts = list(states) + [workloads.uniform_state(n, b, seed=6) for n, b, _ in extra]
     bxs = [float(b) for b in boxes] + [b for _, b, _ in extra]
     reaches = [0] * len(ns) + [r for _, _, r in extra]
@@ -346,7 +351,7 @@ def test_per_env_fused_sort_batch_bitwise_and_oracle():
         assert torch.equal(ea.returns(), eb.returns())
         assert all(torch.equal(u, w) for u, w in zip(ea.get_state(), eb.get_state()))
     g = np.random.default_rng(4)
-    for k in range(0, len(sts), 10):
+    for k in sorted(set(range(0, len(sts), 10)) | {len(sts) - 1}):
         st = sts[k]
         for t in range(6):
             st = oracle.oracle_move(st, acts_all[t][k], bxs[k])

@@ -334,9 +334,11 @@ def cpu_baseline(seconds):
 def sweep_work(envs, radius=8.0):
     """Candidate tests and neighbour pairs of one sweep over these envs' current states.
 
-    Candidates: for each agent, every agent of the (2 reach + 1)^2 cells round
-    its own (itself included; all n in a single-cell env).  Neighbours:
-    ordered pairs closer than the vision range (periodic k-d tree).
+    Candidates are those of the textbook cell list, independent of the grid
+    the kernels use: for each agent, every agent of the 3 x 3 block of square
+    cells of side at least the vision range round its own (itself included;
+    all n when fewer than 3 such cells fit the side).  Neighbours: ordered
+    pairs closer than the vision range (periodic k-d tree).
     """
     from scipy.spatial import cKDTree
     cand = nbrs = 0
@@ -346,8 +348,8 @@ def sweep_work(envs, radius=8.0):
         if n == 0:
             continue
         box = e.params.box
-        nc, reach, _ = e.geometry()
-        if nc == 1:
+        nc, reach = int(box // e.params.radius), 1
+        if nc < 3:
             cand += n * n
         else:
             cx = np.minimum((x * (nc / box)).astype(np.int64), nc - 1)

@@ -76,8 +76,8 @@ enum {
  * nearest periodic image is unique within the vision range);
  * 0 <= collide <= radius; 1 <= sectors <= 256; max_turn, max_dspeed >= 0;
  * 0 <= s_min <= s_max; all finite; cell_reach in {0, 1, 2} (0 = default 1):
- * cells are at least radius/cell_reach wide, so a (2 cell_reach + 1)^2 block
- * of cells covers the vision disc.  Boxes narrower than three cells use a
+ * grid columns are at least radius/cell_reach wide, so 2 cell_reach + 1 of
+ * them cover the vision disc.  Boxes narrower than three columns use a
  * single cell and compare all pairs; the result does not depend on this.
  * fov: field of view in radians, in [0, 2pi] (FP32 2pi); 0 and 2pi mean
  * all round (Sec. 5 uses about 250 degrees).  With a full view sector 0 starts at the heading;
@@ -137,12 +137,18 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
 /* Release the handle (not the workspace).  NULL is ignored. */
 void env_destroy(env_t *env);
 
-/* Effective cell grid: cells per side (1 = all-pairs), reach, cell side. */
-int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell);
+/* Effective cell grid: ncx columns of width cell_w (at least radius /
+ * reach; 1 column = all pairs), each cut into ncy rows of height cell_h
+ * (ncy = 4 ncx, or 1 for all pairs); the sweep visits 2 reach + 1 columns
+ * and, in each, only the rows that can hold a point within the vision
+ * radius.  Any output pointer may be NULL.  ENV_EINVAL for a NULL env. */
+int env_geometry(const env_t *env, int32_t *ncx, int32_t *ncy, int32_t *reach, float *cell_w,
+                 float *cell_h);
 
 /* Lanes of the neighbour sweep that share one agent's candidates (a lane
  * group inside a wavefront): 1, 4, 16 or 64, or 0 to choose from the
- * expected candidates per agent (about (2 cell_reach + 1)^2 n / ncell^2).
+ * expected candidates per agent (about n (2 reach + 1) cell_w (2 radius +
+ * cell_h) / box^2).
  * Results do not depend on it; sparse neighbourhoods favour 1, dense ones
  * (hundreds of candidates per agent) larger groups.  ENV_EINVAL for other
  * values. */

@@ -81,19 +81,27 @@ int check_params(const env_params_t *p) {
 bool valid_lanes(int lanes) { return lanes == 1 || lanes == 4 || lanes == 16 || lanes == 64; }
 
 struct Geometry {
-    int ncell, reach;
-    float cell, inv_cell;
+    int ncx, ncy, reach;
+    float cw, ch, inv_cx, inv_cy, marg;
 };
 
-// Cells are at least radius/reach wide after FP32 rounding of the cell
-// boundaries: floor(x * inv_cell) moves a boundary by at most box * 2^-23,
+// Rows per column: a column's candidates are the rows within the vision
+// range of the agent's y, so rows far narrower than the range trim the
+// stencil to the disc more closely; a run costs the same however many rows
+// it spans.
+constexpr int kRowsPerColumnWidth = 4;
+
+// Columns are at least radius/reach wide after FP32 rounding of the cell
+// boundaries: floor(x * inv_cx) moves a boundary by at most box * 2^-23,
 // so the nominal width carries a margin of 4 * box * 2^-23.  The grid is
-// also capped near sqrt(4n) cells per side so empty boxes stay cheap
-// (wider cells only add candidates).  Fewer than 2 reach + 1 cells per
-// side would visit a cell twice, so such boxes fall back to one cell and
-// all pairs.
+// also capped near sqrt(4n) columns so empty boxes stay cheap (wider
+// columns only add candidates).  Fewer than 2 reach + 1 columns would visit
+// a column twice, so such boxes fall back to one cell and all pairs.  Each
+// column holds kRowsPerColumnWidth times as many rows; the sweep widens its
+// row bounds by marg = box * 2^-20, well above the rounding of the row
+// assignment, of the bounds themselves and of the pair test.
 Geometry geometry(const env_params_t &p) {
-    Geometry g{1, 0, p.box, 0.0f};
+    Geometry g{1, 1, 0, p.box, p.box, 0.0f, 0.0f, 0.0f};
     const double L = p.box, R = p.radius;
     const double margin = 4.0 * L * ldexp(1.0, -23);
     const int64_t cap = (int64_t)ceil(sqrt(4.0 * (double)(p.n_agents > 0 ? p.n_agents : 1))) + 3;
@@ -102,10 +110,14 @@ Geometry geometry(const env_params_t &p) {
         if (nc > cap) nc = cap;
         if (nc > 8192) nc = 8192;
         if (nc >= 2 * r + 1) {
-            g.ncell = (int)nc;
+            g.ncx = (int)nc;
+            g.ncy = (int)nc * kRowsPerColumnWidth;
             g.reach = r;
-            g.cell = (float)(L / (double)nc);
-            g.inv_cell = (float)((double)nc / L);
+            g.cw = (float)(L / (double)g.ncx);
+            g.ch = (float)(L / (double)g.ncy);
+            g.inv_cx = (float)((double)g.ncx / L);
+            g.inv_cy = (float)((double)g.ncy / L);
+            g.marg = (float)(L * ldexp(1.0, -20));
             return g;
         }
     }
@@ -116,10 +128,14 @@ DevEnv make_desc(const env_params_t &p, const Geometry &gm) {
     DevEnv d;
     memset(&d, 0, sizeof(d));
     d.n = p.n_agents;
-    d.ncell = gm.ncell;
+    d.ncx = gm.ncx;
+    d.ncy = gm.ncy;
     d.reach = gm.reach;
     d.box = p.box;
-    d.inv_cell = gm.inv_cell;
+    d.inv_cx = gm.inv_cx;
+    d.inv_cy = gm.inv_cy;
+    d.cw = gm.cw;
+    d.marg = gm.marg;
     d.r2 = p.radius * p.radius;
     d.c2 = p.collide * p.collide;
     d.inv_radius = (float)(1.0 / (double)p.radius);
@@ -168,7 +184,7 @@ EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
     const bool counts = (p.flags & ENV_FLAG_COUNTS) != 0;
     l.nb = counts ? cv.take<int32_t>(n) : nullptr;
     l.col = counts ? cv.take<int32_t>(n) : nullptr;
-    carve_sort(cv, n, (int64_t)gm.ncell * gm.ncell, 1, &l.sort);
+    carve_sort(cv, n, (int64_t)gm.ncx * gm.ncy, 1, &l.sort);
     l.bytes = align_up(cv.off, 256);
     return l;
 }
@@ -264,13 +280,22 @@ int validate_params(const env_params_t *p) { return check_params(p); }
 
 DevEnv env_descriptor(const env_t *env, int flip) { return orient(env, env->parity ^ (flip & 1)); }
 
-int64_t env_cell_count(const env_t *env) { return (int64_t)env->gm.ncell * env->gm.ncell; }
+int64_t env_cell_count(const env_t *env) { return (int64_t)env->gm.ncx * env->gm.ncy; }
 
+int64_t cell_count_for(const env_params_t &p) {
+    const Geometry g = geometry(p);
+    return (int64_t)g.ncx * g.ncy;
+}
+
+// The stencil's area before trimming to the disc: 2 reach + 1 columns, each
+// 2 radius + one row high.
 double env_candidates_per_agent(const env_t *env) {
     const double n = env->p.n_agents;
-    if (env->gm.ncell == 1) return n;
-    const double w = 2.0 * env->gm.reach + 1.0, nc = env->gm.ncell;
-    return n * w * w / (nc * nc);
+    const Geometry &g = env->gm;
+    if (g.ncx == 1) return n;
+    const double L = env->p.box;
+    const double area = (2.0 * g.reach + 1.0) * g.cw * (2.0 * env->p.radius + g.ch);
+    return n * std::min(1.0, area / (L * L));
 }
 
 // One lane per agent suits a few dozen candidates.  Beyond that a lane group
@@ -400,7 +425,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.a = e->lay.sort;
     e->plan.n_envs = 1;
     e->plan.G = p->n_agents;
-    e->plan.C = (int64_t)gm.ncell * gm.ncell;
+    e->plan.C = (int64_t)gm.ncx * gm.ncy;
     e->plan.v = p->sectors;
     e->plan.obs_dim = obs_dim_of(*p);
     e->plan.fov = full_view(*p) ? 0 : 1;
@@ -416,11 +441,14 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
 
 void env_destroy(env_t *env) { delete env; }
 
-int env_geometry(const env_t *env, int32_t *ncell, int32_t *reach, float *cell) {
+int env_geometry(const env_t *env, int32_t *ncx, int32_t *ncy, int32_t *reach, float *cell_w,
+                 float *cell_h) {
     if (!env) return fail(ENV_EINVAL, "env is NULL");
-    if (ncell) *ncell = env->gm.ncell;
+    if (ncx) *ncx = env->gm.ncx;
+    if (ncy) *ncy = env->gm.ncy;
     if (reach) *reach = env->gm.reach;
-    if (cell) *cell = env->gm.cell;
+    if (cell_w) *cell_w = env->gm.cw;
+    if (cell_h) *cell_h = env->gm.ch;
     return ENV_OK;
 }
 
@@ -525,7 +553,7 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *ba
         if (base) base->push_back((int32_t)g);
         if (off) off->push_back(g);
         g += e->p.n_agents;
-        c += (int64_t)e->gm.ncell * e->gm.ncell;
+        c += (int64_t)e->gm.ncx * e->gm.ncy;
         if (g > kMaxBatchAgents || c > kMaxBatchCells)
             return fail(ENV_EINVAL, "batch exceeds 2^30 agents or 2^28 cells");
     }
@@ -659,7 +687,7 @@ static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
     int64_t c = 0;
     for (int k = 0; k < E; ++k) {
         b->tab[0][k].cell_base = b->tab[1][k].cell_base = (int32_t)c;
-        c += (int64_t)b->envs[k]->gm.ncell * b->envs[k]->gm.ncell;
+        c += (int64_t)b->envs[k]->gm.ncx * b->envs[k]->gm.ncy;
         b->base_par[k] = b->envs[k]->parity;
     }
     hipError_t e = hipSuccess;

@@ -35,10 +35,14 @@ struct DevEnv {
     int32_t n;                   // agents
     int32_t agent_base;          // first row of this env in batch-wide arrays
     int32_t cell_base;           // first cell of this env in the batch cell space
-    int32_t ncell;               // cells per side (1 = all pairs)
-    int32_t reach;               // stencil half-width in cells (0 when ncell == 1)
+    // Cell grid: ncx columns of width cw (at least radius / reach), each cut
+    // into ncy rows; cell = column * ncy + row.  ncx == 1: all pairs.
+    int32_t ncx, ncy;
+    int32_t reach;               // stencil half-width in columns (0 when ncx == 1)
     float box;                   // L
-    float inv_cell;              // FP32 multiplier: cell = floor(x * inv_cell)
+    float inv_cx, inv_cy;        // FP32 multipliers: column = floor(x * inv_cx), row likewise
+    float cw;                    // column width L / ncx (FP32)
+    float marg;                  // widening of the row bounds for FP32 rounding
     float r2;                    // radius^2 (FP32)
     float c2;                    // collide^2 (FP32)
     float inv_radius;            // 1 / radius (FP32)
@@ -153,6 +157,7 @@ int auto_lanes(double cand, int v);
 // the env's current buffer (flip = 1 swaps cur and nxt).
 DevEnv env_descriptor(const env_t *env, int flip);
 int64_t env_cell_count(const env_t *env);       // cells of this env's grid
+int64_t cell_count_for(const env_params_t &p);  // cells an env of these params uses
 const env_params_t &env_params(const env_t *env);
 int env_parity(const env_t *env);
 void env_advance(env_t *env, int steps);        // record `steps` stepped elsewhere

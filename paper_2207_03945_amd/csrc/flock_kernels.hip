@@ -143,9 +143,9 @@ __device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 
     return make_float4(nx, ny, h, sp);
 }
 
-// Cell of a position within its env's grid.
+// Cell of a position within its env's grid: column-major, rows within a column.
 __device__ __forceinline__ int local_cell(const DevEnv &E, float x, float y) {
-    return cell_of(x, E.inv_cell, E.ncell) * E.ncell + cell_of(y, E.inv_cell, E.ncell);
+    return cell_of(x, E.inv_cx, E.ncx) * E.ncy + cell_of(y, E.inv_cy, E.ncy);
 }
 
 // Records per thread of the move kernel: a block covers kMoveRecs * kBlock
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_scan_env(int32_t *__restrict__ count,
     __shared__ int s_tile[NT * ITEMS];
     const int t = threadIdx.x;
     const DevEnv &E = envs[blockIdx.x];
-    const int cb = E.cell_base, Ce = E.ncell * E.ncell, base = E.agent_base;
+    const int cb = E.cell_base, Ce = E.ncx * E.ncy, base = E.agent_base;
     count += cb;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     __shared__ int s_wave[kEnvNT / 64 + 1];
     const int tid = threadIdx.x;
     const DevEnv &E = envs[blockIdx.x];
-    const int n = E.n, base = E.agent_base, cb = E.cell_base, Ce = E.ncell * E.ncell;
+    const int n = E.n, base = E.agent_base, cb = E.cell_base, Ce = E.ncx * E.ncy;
     for (int c = tid; c < Ce; c += kEnvNT) s_cells[c] = 0;
     __syncthreads();
     constexpr bool kRegs = R <= kEnvRegR;
@@ -719,12 +719,47 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
     for (; q < q1; q += G) test(sxy[q], q);
 }
 
+// Rows [lo, hi] of the column ox columns from the agent's own that can hold
+// a point within the vision radius: the column's nearest x lies dmin from
+// the agent, so only |dy| < sqrt(R^2 - dmin^2) matters.  fx is the agent's
+// offset within its own column.  Both bounds widen by E.marg, which covers
+// the FP32 rounding of the row assignment, of these bounds and of the pair
+// test.  hi - lo < ncy; lo < 0 or hi >= ncy wrap through the column's ends.
+// False when no point of the column is within the radius.
+struct RowGeom {
+    float cw, marg, r2, inv_cy;
+    int ncy;
+};
+
+__device__ __forceinline__ bool column_rows(const RowGeom &E, float fx, int ox, float y, int &lo,
+                                            int &hi) {
+    float dmin = 0.0f;
+    if (ox < 0) dmin = fx + (float)(-ox - 1) * E.cw;
+    else if (ox > 0) dmin = (E.cw - fx) + (float)(ox - 1) * E.cw;
+    dmin = fmaxf(dmin - E.marg, 0.0f);
+    const float e2 = E.r2 - dmin * dmin;
+    if (!(e2 > 0.0f)) return false;
+    const float ext = __builtin_amdgcn_sqrtf(e2) + E.marg;  // within 1 ulp
+    const int n = E.ncy;
+    int l = (int)floorf((y - ext) * E.inv_cy);
+    int h = (int)floorf((y + ext) * E.inv_cy);
+    // in range for finite positions in [0, L); the clamps keep any other
+    // input inside the column (memory safety only)
+    l = max(min(l, n - 1), -n);
+    h = max(min(h, l + n - 1), l);
+    lo = l;
+    hi = h;
+    return true;
+}
+
 // Candidates per loop iteration of the sweep (independent loads in flight).
 constexpr int kUnroll = 4;
-// One lane per agent: walk the block's runs as one sequence (a lane moves to
-// its next run as soon as its current one ends) instead of run by run, so a
-// wave waits for its longest total rather than for the longest lane of every
-// run (on MI355X: 96 -> 83 us for 1M agents at 30 candidates each).
+// One lane per agent, stencil half-width 1: walk the agent's runs as one
+// sequence (a lane moves to its next run as soon as its current one ends)
+// instead of run by run, so a wave waits for its longest total rather than
+// for the longest lane of every run.  The runs are found once per agent and
+// queued in registers: lanes switch runs at different steps, so whatever a
+// switch costs is paid by the whole wave on nearly every step.
 constexpr bool kFlatRuns = true;
 constexpr int kFlatUnroll = 2;  // candidates per step while a run has that many left
 
@@ -776,7 +811,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         const ViewK K{c, s, E.fov_half, E.fov_t, E.sec_scale, (float)v, v};
         ti = kTag ? (E.id_nxt[j] < E.n_chasers ? 1 : 0) : 0;
         const float L = E.box, r2 = E.r2, c2 = E.c2;
-        const int ncell = E.ncell, cb = E.cell_base;
+        const int ncx = E.ncx, ncy = E.ncy, cb = E.cell_base;
         // one run of candidates [q, q1): template flags say which shifts are nonzero
         auto run = [&](auto sx, auto sy, int q, int q1, float offx, float xi, float offy, float yi,
                        bool minimg) {
@@ -786,84 +821,92 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         };
         using No = std::false_type;
         using Yes = std::true_type;
-        if (ncell == 1) {
+        if (ncx == 1) {
             run(No{}, No{}, a.start[cb], a.start[cb + 1], 0.0f, me.x, 0.0f, me.y, true);
         } else {
             const int reach = E.reach;
-            const int cx = cell_of(me.x, E.inv_cell, ncell);
-            const int cy = cell_of(me.y, E.inv_cell, ncell);
-            const int lo = cy - reach, hi = cy + reach;
-            // the column's runs; a column left of cell 0 wraps to the right
-            // edge with its candidates shifted by -L (sx), one right of the
-            // last wraps to the left edge with the centre shifted instead
-            auto column = [&](auto sx, int colb, float offx, float xi) {
+            const int cx = cell_of(me.x, E.inv_cx, ncx);
+            const float fx = me.x - (float)cx * E.cw;  // offset within the own column
+            const RowGeom RG{E.cw, E.marg, r2, E.inv_cy, ncy};  // held in registers
+            // the column's runs over rows [lo, hi]; a column left of column 0
+            // wraps to the right edge with its candidates shifted by -L (sx),
+            // one right of the last wraps to the left edge with the centre
+            // shifted instead; rows wrap likewise
+            auto column = [&](auto sx, int colb, float offx, float xi, int lo, int hi) {
                 if (lo < 0) {
-                    run(sx, Yes{}, a.start[colb + lo + ncell], a.start[colb + ncell], offx, xi, -L,
+                    run(sx, Yes{}, a.start[colb + lo + ncy], a.start[colb + ncy], offx, xi, -L,
                         me.y, false);
                     run(sx, No{}, a.start[colb], a.start[colb + hi + 1], offx, xi, 0.0f, me.y, false);
-                } else if (hi >= ncell) {
-                    run(sx, No{}, a.start[colb + lo], a.start[colb + ncell], offx, xi, 0.0f, me.y,
+                } else if (hi >= ncy) {
+                    run(sx, No{}, a.start[colb + lo], a.start[colb + ncy], offx, xi, 0.0f, me.y,
                         false);
-                    run(sx, No{}, a.start[colb], a.start[colb + hi - ncell + 1], offx, xi, 0.0f,
+                    run(sx, No{}, a.start[colb], a.start[colb + hi - ncy + 1], offx, xi, 0.0f,
                         me.y - L, false);
                 } else {
                     run(sx, No{}, a.start[colb + lo], a.start[colb + hi + 1], offx, xi, 0.0f, me.y,
                         false);
                 }
             };
-            if constexpr (G == 1 && kFlatRuns) {
-                // run state: column oxi of 2 reach + 1, segment seg of the column
-                int oxi = 0, seg = 0, q = 0, q1 = 0;
+            if (G == 1 && kFlatRuns && reach == 1) {
+                // The agent's runs, built once: slot c (c < 3) is column c - 1's
+                // first segment, slot 3 + c its second (empty unless the rows
+                // wrap).  Per slot 4 bits of shift flags: 1 candidate x - L,
+                // 2 centre x - L, 4 candidate y - L, 8 centre y - L.
+                int rq[6], rq1[6];
+                uint32_t fl = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    int lo = 0, hi = -1;
+                    const bool any = column_rows(RG, fx, c - 1, me.y, lo, hi);
+                    int ccx = cx + c - 1;
+                    uint32_t fxs = 0;
+                    if (ccx < 0) {
+                        ccx += ncx;
+                        fxs = 1;
+                    } else if (ccx >= ncx) {
+                        ccx -= ncx;
+                        fxs = 2;
+                    }
+                    const int colb = cb + ccx * ncy;
+                    const bool wlo = lo < 0, whi = hi >= ncy;
+                    // first segment [ia, ib), second [colb, colb + id - colb)
+                    int ia = colb + (wlo ? lo + ncy : lo);
+                    int ib = colb + ((wlo || whi) ? ncy : hi + 1);
+                    int id = colb + (wlo ? hi + 1 : (whi ? hi - ncy + 1 : 0));
+                    if (!any) ia = ib = id = colb;
+                    rq[c] = a.start[ia];
+                    rq1[c] = a.start[ib];
+                    rq[3 + c] = a.start[colb];
+                    rq1[3 + c] = a.start[id];
+                    fl |= (fxs | (wlo ? 4u : 0u)) << (4 * c);
+                    fl |= (fxs | (whi ? 8u : 0u)) << (4 * (3 + c));
+                }
+                int q = 0, q1 = 0, left = 6;
                 float offx = 0.0f, xi = me.x, offy = 0.0f, yi = me.y;
-                auto next_run = [&]() -> bool {
-                    while (oxi <= 2 * reach) {
-                        int ccx = cx - reach + oxi;
-                        offx = 0.0f;
-                        xi = me.x;
-                        if (ccx < 0) {
-                            ccx += ncell;
-                            offx = -L;
-                        } else if (ccx >= ncell) {
-                            ccx -= ncell;
-                            xi = me.x - L;
+                // move to the next nonempty slot; false when none is left
+                auto advance = [&]() -> bool {
+                    while (left > 0) {
+                        q = rq[0];
+                        q1 = rq1[0];
+                        const uint32_t f = fl;
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            rq[k] = rq[k + 1];
+                            rq1[k] = rq1[k + 1];
                         }
-                        const int colb = cb + ccx * ncell;
-                        offy = 0.0f;
-                        yi = me.y;
-                        int nseg = 1;
-                        if (lo < 0) {
-                            nseg = 2;
-                            if (seg == 0) {
-                                q = a.start[colb + lo + ncell];
-                                q1 = a.start[colb + ncell];
-                                offy = -L;
-                            } else {
-                                q = a.start[colb];
-                                q1 = a.start[colb + hi + 1];
-                            }
-                        } else if (hi >= ncell) {
-                            nseg = 2;
-                            if (seg == 0) {
-                                q = a.start[colb + lo];
-                                q1 = a.start[colb + ncell];
-                            } else {
-                                q = a.start[colb];
-                                q1 = a.start[colb + hi - ncell + 1];
-                                yi = me.y - L;
-                            }
-                        } else {
-                            q = a.start[colb + lo];
-                            q1 = a.start[colb + hi + 1];
+                        fl >>= 4;
+                        --left;
+                        if (q < q1) {
+                            offx = (f & 1u) ? -L : 0.0f;
+                            xi = (f & 2u) ? me.x - L : me.x;
+                            offy = (f & 4u) ? -L : 0.0f;
+                            yi = (f & 8u) ? me.y - L : me.y;
+                            return true;
                         }
-                        if (++seg >= nseg) {
-                            seg = 0;
-                            ++oxi;
-                        }
-                        if (q < q1) return true;
                     }
                     return false;
                 };
-                bool more = next_run();
+                bool more = advance();
                 while (more) {
                     if (q + kFlatUnroll <= q1) {
                         float2 pj[kFlatUnroll];
@@ -881,14 +924,16 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                                                                  r2, c2, K, nb, col);
                         ++q;
                     }
-                    if (q >= q1) more = next_run();
+                    if (q >= q1) more = advance();
                 }
             } else {
                 for (int ox = -reach; ox <= reach; ++ox) {
+                    int lo, hi;
+                    if (!column_rows(RG, fx, ox, me.y, lo, hi)) continue;
                     const int ccx = cx + ox;
-                    if (ccx < 0) column(Yes{}, cb + (ccx + ncell) * ncell, -L, me.x);
-                    else if (ccx >= ncell) column(No{}, cb + (ccx - ncell) * ncell, 0.0f, me.x - L);
-                    else column(No{}, cb + ccx * ncell, 0.0f, me.x);
+                    if (ccx < 0) column(Yes{}, cb + (ccx + ncx) * ncy, -L, me.x, lo, hi);
+                    else if (ccx >= ncx) column(No{}, cb + (ccx - ncx) * ncy, 0.0f, me.x - L, lo, hi);
+                    else column(No{}, cb + ccx * ncy, 0.0f, me.x, lo, hi);
                 }
             }
         }

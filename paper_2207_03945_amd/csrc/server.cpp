@@ -276,9 +276,7 @@ size_t srv_request_bytes(const env_params_t *p) {
     const size_t ws = align_up(env_workspace_bytes(p), 256);
     // its share of the batch sort scratch: per agent and per cell arrays
     const int64_t n = p->n_agents;
-    const double L = p->box, R = p->radius;
-    const int64_t ncell = (int64_t)floor(L / R) + 1;
-    const size_t share = sort_scratch_bytes(n, ncell * ncell, 1);
+    const size_t share = sort_scratch_bytes(n, cell_count_for(*p), 1);
     return ws + io_bytes(*p) + share;
 }
 

@@ -92,6 +92,8 @@ def lib():
         "env_destroy": (None, [_P]),
         "env_geometry": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_float)]),
         "env_set_state": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
         "env_get_state": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -209,9 +211,13 @@ class Env:
             self.handle = None
 
     def geometry(self):
-        nc, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
-        check(lib().env_geometry(self.handle, ctypes.byref(nc), ctypes.byref(r), ctypes.byref(c)))
-        return nc.value, r.value, c.value
+        """(ncx, ncy, reach, cell_w, cell_h): columns, rows per column, stencil
+        half-width in columns, column width, row height."""
+        nx, ny, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cw, ch = ctypes.c_float(), ctypes.c_float()
+        check(lib().env_geometry(self.handle, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(r),
+                                 ctypes.byref(cw), ctypes.byref(ch)))
+        return nx.value, ny.value, r.value, cw.value, ch.value
 
     def set_sweep_lanes(self, lanes: int):
         """Lanes per agent in the neighbour sweep (1, 4, 16, 64; 0 = automatic)."""

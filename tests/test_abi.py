@@ -83,9 +83,13 @@ def test_create_errors_without_gpu():
     # a valid bind makes no HIP call, so it succeeds on a host address
     rc, h, _ = _create()
     assert rc == fe.ENV_OK
-    nc, reach, cell = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
-    assert lib.env_geometry(h, ctypes.byref(nc), ctypes.byref(reach), ctypes.byref(cell)) == 0
-    assert (nc.value, reach.value) == (7, 1) and cell.value > 8.0
+    nx, ny, reach = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    cw, ch = ctypes.c_float(), ctypes.c_float()
+    assert lib.env_geometry(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(reach),
+                            ctypes.byref(cw), ctypes.byref(ch)) == 0
+    assert (nx.value, ny.value, reach.value) == (7, 28, 1) and cw.value > 8.0
+    assert lib.env_geometry(h, None, None, None, None, None) == 0
+    assert lib.env_geometry(None, None, None, None, None, None) == fe.ENV_EINVAL
     # call order: step / reset / counts before their preconditions
     assert lib.env_step(h, 1 << 20, 1 << 20, 1 << 20, None) == fe.ENV_ESTATE
     assert lib.env_reset(h, 1 << 20, None) == fe.ENV_ESTATE
@@ -97,25 +101,34 @@ def test_create_errors_without_gpu():
     assert lib.env_step(None, None, None, None, None) == fe.ENV_EINVAL
 
 
+def _geometry(h):
+    nx, ny, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    cw, ch = ctypes.c_float(), ctypes.c_float()
+    assert fe.lib().env_geometry(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(r),
+                                 ctypes.byref(cw), ctypes.byref(ch)) == 0
+    return nx.value, ny.value, r.value, cw.value, ch.value
+
+
 @pytest.mark.parametrize("box,ncell,reach", [(64.0, 7, 1), (316.0, 39, 1), (1000.0, 124, 1),
                                              (20.0, 1, 0), (24.0, 1, 0), (24.5, 3, 1)])
 def test_geometry(box, ncell, reach):
     rc, h, _ = _create(n_agents=50000, box=box)
     assert rc == 0
-    nc, r, cell = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
-    fe.lib().env_geometry(h, ctypes.byref(nc), ctypes.byref(r), ctypes.byref(cell))
-    assert (nc.value, r.value) == (ncell, reach)
+    nx, ny, r, cw, ch = _geometry(h)
+    assert (nx, r) == (ncell, reach)
     if ncell > 1:
-        # every cell is wider than the vision range plus the rounding margin
+        # every column is wider than the vision range plus the rounding margin
         assert box / ncell >= 8.0 + 4 * box * 2.0 ** -23
+        assert ny == 4 * nx and cw == np.float32(box / nx) and ch == np.float32(box / ny)
+    else:
+        assert ny == 1
     fe.lib().env_destroy(h)
 
 
 def test_reach_two_geometry():
     rc, h, _ = _create(n_agents=50000, box=160.0, cell_reach=2)
-    nc, r, cell = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
-    fe.lib().env_geometry(h, ctypes.byref(nc), ctypes.byref(r), ctypes.byref(cell))
-    assert r.value == 2 and 160.0 / nc.value >= 4.0
+    nx, ny, r, cw, ch = _geometry(h)
+    assert r == 2 and 160.0 / nx >= 4.0 and ny == 4 * nx
     fe.lib().env_destroy(h)
 
 

@@ -165,7 +165,7 @@ def test_small_boxes_all_pairs_and_three_cells(box):
     n = int(box * box / 4)
     st = workloads.uniform_state(n, box, seed=3)
     env = _one_step_case(st, box, 16)
-    ncell, reach, _ = env.geometry()
+    ncell, _, reach, _, _ = env.geometry()
     assert (ncell == 1) == (box <= 24.0)
     assert ncell == 1 or ncell >= 3
 
@@ -179,7 +179,7 @@ def test_sector_counts(v):
 def test_reach_two_stencil():
     st = workloads.uniform_state(4000, 160.0, seed=4)
     env = _one_step_case(st, 160.0, 16, reach=2)
-    assert env.geometry()[1] == 2
+    assert env.geometry()[2] == 2
 
 
 def test_dense_cluster_and_coincident():
@@ -196,13 +196,14 @@ def test_dense_cluster_and_coincident():
 
 
 def test_cell_boundaries_and_seams():
-    """Agents exactly on cell boundaries, at 0 and just below the box side."""
+    """Agents exactly on column and row boundaries, at 0 and just below the box side."""
     box, v = 64.0, 16
     env0 = flock.Env(flock.Params(n_agents=10000, box=box, sectors=v))
-    ncell, _, cell = env0.geometry()
-    xs = np.array([k * cell for k in range(ncell)] + [0.0, np.nextafter(np.float32(box), np.float32(0))],
-                  np.float32)
-    xx, yy = np.meshgrid(xs, xs, indexing="ij")
+    ncx, ncy, _, cw, ch = env0.geometry()
+    top = np.nextafter(np.float32(box), np.float32(0))
+    xs = np.array([k * cw for k in range(ncx)] + [0.0, top], np.float32)
+    ys = np.array([k * ch for k in range(ncy)] + [0.0, top], np.float32)
+    xx, yy = np.meshgrid(xs, ys, indexing="ij")
     x, y = xx.ravel().astype(np.float32), yy.ravel().astype(np.float32)
     n = x.shape[0]
     th = (np.arange(n) * 0.37 % 6.2).astype(np.float32)

@@ -64,11 +64,11 @@ struct SortArrays {
     int32_t *slot;     // [G] rank of record p within its new cell
     float4 *tmp;       // [G] moved record p (old order)
     float2 *sxy;       // [G] positions in the new cell order (candidates)
+    float2 *scs;       // [G] (cos, sin) of the heading, new cell order
     uint8_t *stype;    // [G] tag: 1 for a chaser, in the new cell order
     int32_t *count;    // [C] agents per cell; zero between steps
     int32_t *start;    // [C + 1] exclusive prefix of count
     int32_t *part;     // [scan partials]
-    uint32_t *ticket;  // [1] scan completion counter; zero between steps
     DevEnv *envs[2];   // [E] descriptor tables: [0] as stored, [1] buffers swapped
     int32_t *base;     // [E + 1] agent_base of each env, then G
 };
@@ -116,7 +116,7 @@ int env_sort_recs_for(int n_envs, int64_t max_env_agents, int64_t max_env_cells)
 void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 
 // Launchers (return hipSuccess or the first error) ------------------------
-// Zero count and ticket (used once after carving).
+// Zero the cell counts (used once after carving).
 hipError_t launch_clear(const StepPlan &p, hipStream_t s);
 // One step with descriptor table `table` (0 or 1) of the plan.
 // do_move = 0 senses the current state without moving (episode start).

@@ -116,9 +116,17 @@ __device__ __forceinline__ int wave_max(int x) {
 
 constexpr int kHistBins = 2048;
 
+// (cos h, sin h) of a heading: FP64 sincos, each rounded once to FP32.
+__device__ __forceinline__ float2 heading_cs(float h) {
+    double sd, cd;
+    sincos((double)h, &sd, &cd);
+    return make_float2((float)cd, (float)sd);
+}
+
 // One agent's move (Sec. 4.1): turn, speed update (tag: the action is the
-// speed), integrate with the new heading and speed, wrap into [0, L).
-__device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 av) {
+// speed), integrate with the new heading and speed, wrap into [0, L).  cs
+// receives (cos, sin) of the new heading.
+__device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 av, float2 &cs) {
     float x = r.x, y = r.y, h = r.z, sp = r.w;
     const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
     h = h + turn;
@@ -130,9 +138,8 @@ __device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 
         const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
         sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
     }
-    double sd, cd;
-    sincos((double)h, &sd, &cd);
-    const float c = (float)cd, sn = (float)sd;
+    cs = heading_cs(h);
+    const float c = cs.x, sn = cs.y;
     const float L = E.box;
     float nx = x + sp * c;
     if (nx < 0.0f) nx = nx + L;
@@ -197,7 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
         if (!live[r]) continue;
         const int p = p0 + r * kBlock + threadIdx.x;
         const DevEnv &E = envs[env[r]];
-        const float4 m = do_move ? move_record(E, rec[r], av[r]) : rec[r];
+        float2 cs;
+        const float4 m = do_move ? move_record(E, rec[r], av[r], cs) : rec[r];
         a.tmp[p] = m;
         key[r] = E.cell_base + local_cell(E, m.x, m.y);
         a.key[p] = key[r];
@@ -335,14 +343,12 @@ constexpr int kScan2NT = 256;
 constexpr int kScan2Items = 8;
 constexpr int kTile2 = kScan2NT * kScan2Items;
 
-// Phase 1: per-tile sums; the last tile to finish turns the sums into
-// exclusive tile offsets (in chunks of kTile2 with a running carry).
-__global__ __launch_bounds__(kScan2NT) void k_scan_reduce(const int32_t *__restrict__ count,
-                                                          int32_t *__restrict__ part,
-                                                          uint32_t *__restrict__ ticket,
-                                                          int32_t *__restrict__ start, int C) {
+// Phase 1: per-tile totals.  The phases are separate launches, whose
+// boundaries order them; no block waits on another (a device-wide fence per
+// block writes back an XCD's L2 and costs far more than a launch).
+__global__ __launch_bounds__(kScan2NT) void k_tile_sums(const int32_t *__restrict__ count,
+                                                        int32_t *__restrict__ part, int C) {
     __shared__ int s_wave[kScan2NT / 64 + 1];
-    __shared__ int s_last;
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kTile2;
     int sum = 0;
@@ -353,16 +359,18 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_reduce(const int32_t *__restr
     }
     int total;
     (void)block_exclusive_scan<kScan2NT>(sum, s_wave, &total);
-    if (t == 0) {
-        part[blockIdx.x] = total;
-        __threadfence();
-        const uint32_t prev = atomicAdd(ticket, 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int nb = gridDim.x;
+    if (t == 0) part[blockIdx.x] = total;
+}
+
+// Up to this many tiles, each tile of phase 2 sums the totals before it
+// itself; beyond, one block first turns them into exclusive offsets.
+constexpr int kDirectTiles = 4096;
+
+// Phase 1b (more than kDirectTiles tiles): one block, exclusive offsets of
+// the nb tile totals in place, in chunks of kTile2 with a running carry.
+__global__ __launch_bounds__(kScan2NT) void k_scan_parts(int32_t *__restrict__ part, int nb) {
+    __shared__ int s_wave[kScan2NT / 64 + 1];
+    const int t = threadIdx.x;
     int carry = 0;
     for (int c0 = 0; c0 < nb; c0 += kTile2) {
         int vals[kScan2Items];
@@ -370,10 +378,9 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_reduce(const int32_t *__restr
 #pragma unroll
         for (int k = 0; k < kScan2Items; ++k) {
             const int idx = c0 + t * kScan2Items + k;
-            vals[k] = idx < nb ? __atomic_load_n(&part[idx], __ATOMIC_RELAXED) : 0;
+            vals[k] = idx < nb ? part[idx] : 0;
             psum += vals[k];
         }
-        __syncthreads();
         int chunk;
         int run = block_exclusive_scan<kScan2NT>(psum, s_wave, &chunk) + carry;
 #pragma unroll
@@ -383,22 +390,31 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_reduce(const int32_t *__restr
             run += vals[k];
         }
         carry += chunk;
-        __syncthreads();
-    }
-    if (t == 0) {
-        start[C] = carry;
-        *ticket = 0u;
+        __syncthreads();  // s_wave is reused by the next chunk
     }
 }
 
-// Phase 2: scan each tile with its offset; re-zero the counts.
+// Phase 2: scan each tile from its offset; re-zero the counts.  kSum: the
+// offset is the sum of the totals of the tiles before (at most kDirectTiles
+// of them), else part holds the offsets.  The last tile writes start[C].
+template <bool kSum>
 __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ count,
                                                         const int32_t *__restrict__ part,
                                                         int32_t *__restrict__ start, int C) {
     __shared__ int s_wave[kScan2NT / 64 + 1];
     __shared__ int s_tile[kTile2];
+    __shared__ int s_off;
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kTile2;
+    if constexpr (kSum) {
+        int before = 0;
+        for (int b = t; b < (int)blockIdx.x; b += kScan2NT) before += part[b];
+        int sum_before;
+        (void)block_exclusive_scan<kScan2NT>(before, s_wave, &sum_before);
+        if (t == 0) s_off = sum_before;
+    } else {
+        if (t == 0) s_off = part[blockIdx.x];
+    }
 #pragma unroll
     for (int k = 0; k < kScan2Items; ++k) {
         const int64_t idx = base + k * kScan2NT + t;
@@ -413,12 +429,14 @@ __global__ __launch_bounds__(kScan2NT) void k_scan_down(int32_t *__restrict__ co
         sum += vals[k];
     }
     int total;
-    int run = block_exclusive_scan<kScan2NT>(sum, s_wave, &total) + part[blockIdx.x];
+    const int off = s_off;  // published before the scan's barriers
+    int run = block_exclusive_scan<kScan2NT>(sum, s_wave, &total) + off;
 #pragma unroll
     for (int k = 0; k < kScan2Items; ++k) {
         s_tile[t * kScan2Items + k] = run;
         run += vals[k];
     }
+    if (t == 0 && blockIdx.x == gridDim.x - 1) start[C] = off + total;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kScan2Items; ++k) {
@@ -459,6 +477,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     constexpr int RR = kRegs ? R : 1;
     int key[R], rank[R];
     float4 mr[RR];
+    float2 csr[RR];
     int idr[RR];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -468,13 +487,17 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         if (i < n) {
             float4 m = E.rec_cur[i];
             const int id = E.id_cur[i];
+            float2 cs = make_float2(0.0f, 0.0f);
             if (do_move) {
                 const float2 av =
                     act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
-                m = move_record(E, m, av);
+                m = move_record(E, m, av, cs);
+            } else if constexpr (kRegs) {
+                cs = heading_cs(m.z);
             }
             if constexpr (kRegs) {
                 mr[r] = m;
+                csr[r] = cs;
                 idr[r] = id;
             } else {
                 a.tmp[base + i] = m;
@@ -505,15 +528,19 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         if (i < n) {
             const int j = s_cells[key[r]] + rank[r];
             float4 m;
+            float2 cs;
             int id;
             if constexpr (kRegs) {
                 m = mr[r];
+                cs = csr[r];
                 id = idr[r];
             } else {
                 m = a.tmp[base + i];
+                cs = heading_cs(m.z);
                 id = E.id_cur[i];
             }
             E.rec_nxt[j] = m;
+            a.scs[base + j] = cs;
             E.id_nxt[j] = id;
             E.ret_nxt[j] = E.ret_cur[i];
             a.sxy[base + j] = make_float2(m.x, m.y);
@@ -541,6 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *
     const float4 r = a.tmp[p];
     const int id = E.id_cur[i];
     E.rec_nxt[j] = r;
+    a.scs[pos] = heading_cs(r.z);
     E.id_nxt[j] = id;
     E.ret_nxt[j] = E.ret_cur[i];
     a.sxy[pos] = make_float2(r.x, r.y);
@@ -802,9 +830,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     int nb = 0, col = 0, ti = 0;
     if (active) {
         me = E.rec_nxt[j];
-        double sd, cd;
-        sincos((double)me.z, &sd, &cd);
-        const float c = (float)cd, s = (float)sd;
+        const float2 cs = a.scs[pos];
+        const float c = cs.x, s = cs.y;
         if constexpr (G == 1)
             for (int k = 0; k < vs; ++k) smin[k * A] = kInfBits;
 
@@ -987,10 +1014,9 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
 
 // ------------------------------------------------------------------ helpers
 
-__global__ void k_clear(int32_t *count, int64_t C, uint32_t *ticket) {
+__global__ void k_clear(int32_t *count, int64_t C) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < C) count[i] = 0;
-    if (i == 0) *ticket = 0u;
 }
 
 __global__ void k_load_state(const float *x, const float *y, const float *th, const float *sp,
@@ -1051,11 +1077,11 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
     a->sxy = cv.take<float2>(G);
+    a->scs = cv.take<float2>(G);
     a->stype = cv.take<uint8_t>(G);
     a->count = cv.take<int32_t>(C);
     a->start = cv.take<int32_t>(C + 1);
     a->part = cv.take<int32_t>(nb + 1);
-    a->ticket = cv.take<uint32_t>(1);
     a->envs[0] = cv.take<DevEnv>(E);
     a->envs[1] = cv.take<DevEnv>(E);
     a->base = cv.take<int32_t>(E + 1);
@@ -1063,8 +1089,7 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
 
 hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     const int64_t n = p.C > 0 ? p.C : 1;
-    hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C,
-                       p.a.ticket);
+    hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C);
     return hipGetLastError();
 }
 
@@ -1133,10 +1158,17 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
                     hipLaunchKernelGGL((k_scan_env<kScanNT, kScanItems>), dim3(p.n_envs),
                                        dim3(kScanNT), 0, s, p.a.count, p.a.start, envs, p.n_envs, C);
             } else {
-                hipLaunchKernelGGL(k_scan_reduce, dim3(p.scan_blocks), dim3(kScan2NT), 0, s,
-                                   p.a.count, p.a.part, p.a.ticket, p.a.start, C);
-                hipLaunchKernelGGL(k_scan_down, dim3(p.scan_blocks), dim3(kScan2NT), 0, s,
-                                   p.a.count, p.a.part, p.a.start, C);
+                hipLaunchKernelGGL(k_tile_sums, dim3(p.scan_blocks), dim3(kScan2NT), 0, s,
+                                   p.a.count, p.a.part, C);
+                if (p.scan_blocks <= kDirectTiles) {
+                    hipLaunchKernelGGL(k_scan_down<true>, dim3(p.scan_blocks), dim3(kScan2NT), 0,
+                                       s, p.a.count, p.a.part, p.a.start, C);
+                } else {
+                    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScan2NT), 0, s, p.a.part,
+                                       p.scan_blocks);
+                    hipLaunchKernelGGL(k_scan_down<false>, dim3(p.scan_blocks), dim3(kScan2NT), 0,
+                                       s, p.a.count, p.a.part, p.a.start, C);
+                }
             }
             break;
         case kPhaseScatter:

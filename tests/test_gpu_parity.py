@@ -226,6 +226,24 @@ def test_single_large_env():
     check_step(env, st, box, v, obs, rew, agents=agents, label="1M env")
 
 
+def test_sparse_env_many_cells():
+    """2^20 agents in side 16,384: 2,046 columns of 8,184 rows, 16.7M cells, so the
+    cell scan runs with more tiles than its direct-offset limit; sampled agents."""
+    n, box, v = 1 << 20, 16384.0, 16
+    st = workloads.uniform_state(n, box, seed=9)
+    env, _ = make_env(st, box, v)
+    ncx, ncy, _, _, _ = env.geometry()
+    assert ncx * ncy > 4096 * 2048
+    obs = torch.empty(n, v, device="cuda")
+    rew = torch.empty(n, device="cuda")
+    for t in range(2):
+        act = workloads.random_actions(n, seed=9, step=t)
+        env.step(dev(act), obs, rew)
+        st = oracle.oracle_move(st, act, box)
+    agents = np.sort(np.random.default_rng(2).choice(n, 2000, replace=False)).astype(np.int32)
+    check_step(env, st, box, v, obs, rew, agents=agents, label="16.7M-cell env")
+
+
 # --------------------------------------------------------------------------- batched
 
 def _uneven(n_envs, lo, hi, seed):

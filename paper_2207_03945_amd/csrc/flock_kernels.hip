@@ -694,7 +694,8 @@ template <int S, bool kFov, bool kTag, int kM, bool kShiftX, bool kShiftY>
 __device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__restrict__ stype,
                                           int ti, const float2 pj, int qq, int self, float offx,
                                           float xi, float offy, float yi, bool minimg, float L,
-                                          float r2, float c2, const ViewK &K, int &nb, int &col) {
+                                          float r2, float c2, const ViewK &K, int &nb, int &col,
+                                          bool valid = true) {
     float dx, dy;
     if (minimg) {
         dx = min_image_delta(pj.x, xi, L);
@@ -704,7 +705,7 @@ __device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__r
         dy = (kShiftY ? pj.y + offy : pj.y) - yi;
     }
     const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-    const bool nbr = d2 < r2 && qq != self;
+    const bool nbr = valid && d2 < r2 && qq != self;
     int ch = 0;  // view channel offset (sectors)
     if constexpr (kTag) {
         const int tj = stype[qq];
@@ -732,19 +733,20 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
                                           int q, int q1, int li, int self, float offx, float xi,
                                           float offy, float yi, bool minimg, float L, float r2,
                                           float c2, const ViewK &K, int &nb, int &col) {
-    auto test = [&](const float2 pj, int qq) {
+    auto test = [&](const float2 pj, int qq, bool valid) {
         test_pair<S, kFov, kTag, kM, kShiftX, kShiftY>(smin_own, stype, ti, pj, qq, self, offx, xi,
-                                                       offy, yi, minimg, L, r2, c2, K, nb, col);
+                                                       offy, yi, minimg, L, r2, c2, K, nb, col,
+                                                       valid);
     };
-    q += li;
-    for (; q + (UNROLL - 1) * G < q1; q += UNROLL * G) {
+    // UNROLL candidates per lane and step, those past the run's end masked
+    // (the position arrays are padded for the reads)
+    for (q += li; q < q1; q += UNROLL * G) {
         float2 pj[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) pj[u] = sxy[q + u * G];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) test(pj[u], q + u * G);
+        for (int u = 0; u < UNROLL; ++u) test(pj[u], q + u * G, q + u * G < q1);
     }
-    for (; q < q1; q += G) test(sxy[q], q);
 }
 
 // Rows [lo, hi] of the column ox columns from the agent's own that can hold
@@ -780,8 +782,14 @@ __device__ __forceinline__ bool column_rows(const RowGeom &E, float fx, int ox, 
     return true;
 }
 
-// Candidates per loop iteration of the sweep (independent loads in flight).
-constexpr int kUnroll = 4;
+// Candidates per lane and loop step of a lane group's run (independent loads
+// in flight): groups of 16 or 64 lanes split a run into short pieces, where
+// masked slots past its end cost more than fewer loads in flight (MI355X,
+// 128-sector flock at 16 lanes: 209 us at 4, 193 at 2; 4 lanes: 242 at 4,
+// 248 at 2).
+template <int G>
+constexpr int unroll_for() { return G >= 16 ? 2 : 4; }
+constexpr int kUnrollMax = 4;
 // One lane per agent, stencil half-width 1: walk the agent's runs as one
 // sequence (a lane moves to its next run as soon as its current one ends)
 // instead of run by run, so a wave waits for its longest total rather than
@@ -789,7 +797,15 @@ constexpr int kUnroll = 4;
 // queued in registers: lanes switch runs at different steps, so whatever a
 // switch costs is paid by the whole wave on nearly every step.
 constexpr bool kFlatRuns = true;
-constexpr int kFlatUnroll = 2;  // candidates per step while a run has that many left
+constexpr int kFlatUnroll = 6;  // candidates per step (4: 60.5 us, 6: 59.8, 8: 62.0 at 1M agents)
+// Entries past the end of the cell-order position and type arrays, so that a
+// step's reads past the last run stay inside the allocation: a lane reads at
+// most (unroll - 1) * G + G - 1 < kUnrollMax * 64 (lane groups of G <= 64)
+// or kFlatUnroll - 1 entries past its run's end.
+constexpr int kSortPad = 256;
+static_assert(unroll_for<4>() <= kUnrollMax && unroll_for<64>() <= kUnrollMax, "unroll bound");
+static_assert(kFlatUnroll <= kSortPad + 1 && kUnrollMax * 64 <= kSortPad + 1,
+              "pad the cell-order arrays for the unrolled reads");
 
 // NT threads per block, G lanes per agent (in the new cell order): A = NT/G
 // agents per block, their sector minima v * A * 4 bytes of dynamic LDS.  G = 1
@@ -842,7 +858,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         // one run of candidates [q, q1): template flags say which shifts are nonzero
         auto run = [&](auto sx, auto sy, int q, int q1, float offx, float xi, float offy, float yi,
                        bool minimg) {
-            sweep_run<A, G, kUnroll, kFov, kTag, kM, decltype(sx)::value, decltype(sy)::value>(
+            sweep_run<A, G, unroll_for<G>(), kFov, kTag, kM, decltype(sx)::value,
+                      decltype(sy)::value>(
                 smin, a.sxy, a.stype, ti, q, q1, li, pos, offx, xi, offy, yi, minimg, L, r2, c2, K,
                 nb, col);
         };
@@ -935,22 +952,17 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                 };
                 bool more = advance();
                 while (more) {
-                    if (q + kFlatUnroll <= q1) {
-                        float2 pj[kFlatUnroll];
+                    // kFlatUnroll candidates per step, those past the run's end
+                    // masked (the position arrays are padded for the reads)
+                    float2 pj[kFlatUnroll];
 #pragma unroll
-                        for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
+                    for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
 #pragma unroll
-                        for (int u = 0; u < kFlatUnroll; ++u)
-                            test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, pj[u], q + u,
-                                                                     pos, offx, xi, offy, yi, false,
-                                                                     L, r2, c2, K, nb, col);
-                        q += kFlatUnroll;
-                    } else {
-                        test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, a.sxy[q], q,
+                    for (int u = 0; u < kFlatUnroll; ++u)
+                        test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, pj[u], q + u,
                                                                  pos, offx, xi, offy, yi, false, L,
-                                                                 r2, c2, K, nb, col);
-                        ++q;
-                    }
+                                                                 r2, c2, K, nb, col, q + u < q1);
+                    q += kFlatUnroll;
                     if (q >= q1) more = advance();
                 }
             } else {
@@ -1076,9 +1088,9 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->key = cv.take<int32_t>(G);
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
-    a->sxy = cv.take<float2>(G);
+    a->sxy = cv.take<float2>(G + kSortPad);
     a->scs = cv.take<float2>(G);
-    a->stype = cv.take<uint8_t>(G);
+    a->stype = cv.take<uint8_t>(G + kSortPad);
     a->count = cv.take<int32_t>(C);
     a->start = cv.take<int32_t>(C + 1);
     a->part = cv.take<int32_t>(nb + 1);

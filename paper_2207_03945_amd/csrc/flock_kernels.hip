@@ -479,6 +479,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     float4 mr[RR];
     float2 csr[RR];
     int idr[RR];
+    double retr[RR];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = r * kEnvNT + tid;
@@ -499,6 +500,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
                 mr[r] = m;
                 csr[r] = cs;
                 idr[r] = id;
+                retr[r] = E.ret_cur[i];  // loaded now, stored after the scan
             } else {
                 a.tmp[base + i] = m;
             }
@@ -517,11 +519,11 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     for (int c = c0; c < c0 + per && c < Ce; ++c) {
         const int cnt = s_cells[c];
         s_cells[c] = run;
-        a.start[cb + c] = base + run;
         run += cnt;
     }
     if (tid == 0 && blockIdx.x == n_envs - 1) a.start[C] = base + n;
     __syncthreads();
+    for (int c = tid; c < Ce; c += kEnvNT) a.start[cb + c] = base + s_cells[c];  // coalesced
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = r * kEnvNT + tid;
@@ -530,19 +532,22 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
             float4 m;
             float2 cs;
             int id;
+            double ret;
             if constexpr (kRegs) {
                 m = mr[r];
                 cs = csr[r];
                 id = idr[r];
+                ret = retr[r];
             } else {
                 m = a.tmp[base + i];
                 cs = heading_cs(m.z);
                 id = E.id_cur[i];
+                ret = E.ret_cur[i];
             }
             E.rec_nxt[j] = m;
             a.scs[base + j] = cs;
             E.id_nxt[j] = id;
-            E.ret_nxt[j] = E.ret_cur[i];
+            E.ret_nxt[j] = ret;
             a.sxy[base + j] = make_float2(m.x, m.y);
             if (tag) a.stype[base + j] = id < E.n_chasers ? 1 : 0;
         }

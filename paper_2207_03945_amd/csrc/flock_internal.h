@@ -64,7 +64,6 @@ struct SortArrays {
     int32_t *slot;     // [G] rank of record p within its new cell
     float4 *tmp;       // [G] moved record p (old order)
     float2 *sxy;       // [G] positions in the new cell order (candidates)
-    float2 *scs;       // [G] (cos, sin) of the heading, new cell order
     uint8_t *stype;    // [G] tag: 1 for a chaser, in the new cell order
     int32_t *count;    // [C] agents per cell; zero between steps
     int32_t *start;    // [C + 1] exclusive prefix of count

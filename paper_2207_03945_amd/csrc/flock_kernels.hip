@@ -124,9 +124,8 @@ __device__ __forceinline__ float2 heading_cs(float h) {
 }
 
 // One agent's move (Sec. 4.1): turn, speed update (tag: the action is the
-// speed), integrate with the new heading and speed, wrap into [0, L).  cs
-// receives (cos, sin) of the new heading.
-__device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 av, float2 &cs) {
+// speed), integrate with the new heading and speed, wrap into [0, L).
+__device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 av) {
     float x = r.x, y = r.y, h = r.z, sp = r.w;
     const float turn = fminf(fmaxf(av.x, -E.max_turn), E.max_turn);
     h = h + turn;
@@ -138,7 +137,7 @@ __device__ __forceinline__ float4 move_record(const DevEnv &E, float4 r, float2 
         const float ds = fminf(fmaxf(av.y, -E.max_dspeed), E.max_dspeed);
         sp = fminf(fmaxf(sp + ds, E.s_min), E.s_max);
     }
-    cs = heading_cs(h);
+    const float2 cs = heading_cs(h);
     const float c = cs.x, sn = cs.y;
     const float L = E.box;
     float nx = x + sp * c;
@@ -204,8 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
         if (!live[r]) continue;
         const int p = p0 + r * kBlock + threadIdx.x;
         const DevEnv &E = envs[env[r]];
-        float2 cs;
-        const float4 m = do_move ? move_record(E, rec[r], av[r], cs) : rec[r];
+        const float4 m = do_move ? move_record(E, rec[r], av[r]) : rec[r];
         a.tmp[p] = m;
         key[r] = E.cell_base + local_cell(E, m.x, m.y);
         a.key[p] = key[r];
@@ -477,7 +475,6 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     constexpr int RR = kRegs ? R : 1;
     int key[R], rank[R];
     float4 mr[RR];
-    float2 csr[RR];
     int idr[RR];
     double retr[RR];
 #pragma unroll
@@ -488,17 +485,13 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         if (i < n) {
             float4 m = E.rec_cur[i];
             const int id = E.id_cur[i];
-            float2 cs = make_float2(0.0f, 0.0f);
             if (do_move) {
                 const float2 av =
                     act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
-                m = move_record(E, m, av, cs);
-            } else if constexpr (kRegs) {
-                cs = heading_cs(m.z);
+                m = move_record(E, m, av);
             }
             if constexpr (kRegs) {
                 mr[r] = m;
-                csr[r] = cs;
                 idr[r] = id;
                 retr[r] = E.ret_cur[i];  // loaded now, stored after the scan
             } else {
@@ -530,22 +523,18 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
         if (i < n) {
             const int j = s_cells[key[r]] + rank[r];
             float4 m;
-            float2 cs;
             int id;
             double ret;
             if constexpr (kRegs) {
                 m = mr[r];
-                cs = csr[r];
                 id = idr[r];
                 ret = retr[r];
             } else {
                 m = a.tmp[base + i];
-                cs = heading_cs(m.z);
                 id = E.id_cur[i];
                 ret = E.ret_cur[i];
             }
             E.rec_nxt[j] = m;
-            a.scs[base + j] = cs;
             E.id_nxt[j] = id;
             E.ret_nxt[j] = ret;
             a.sxy[base + j] = make_float2(m.x, m.y);
@@ -573,7 +562,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *
     const float4 r = a.tmp[p];
     const int id = E.id_cur[i];
     E.rec_nxt[j] = r;
-    a.scs[pos] = heading_cs(r.z);
     E.id_nxt[j] = id;
     E.ret_nxt[j] = E.ret_cur[i];
     a.sxy[pos] = make_float2(r.x, r.y);
@@ -851,7 +839,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     int nb = 0, col = 0, ti = 0;
     if (active) {
         me = E.rec_nxt[j];
-        const float2 cs = a.scs[pos];
+        const float2 cs = heading_cs(me.z);
         const float c = cs.x, s = cs.y;
         if constexpr (G == 1)
             for (int k = 0; k < vs; ++k) smin[k * A] = kInfBits;
@@ -1094,7 +1082,6 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->slot = cv.take<int32_t>(G);
     a->tmp = cv.take<float4>(G);
     a->sxy = cv.take<float2>(G + kSortPad);
-    a->scs = cv.take<float2>(G);
     a->stype = cv.take<uint8_t>(G + kSortPad);
     a->count = cv.take<int32_t>(C);
     a->start = cv.take<int32_t>(C + 1);

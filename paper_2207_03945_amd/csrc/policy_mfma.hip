@@ -169,9 +169,19 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             const float *src = obs + row0 * in_dim;
             const int cnt = rows * in_dim, cnt4 = cnt >> 2;
             __threadfence_block();  // the previous tile's reads come first
+            // (row, column) of element 4 e4, advanced by 256 elements per step
+            // (no division in the loop)
+            int rb = (4 * lane) / in_dim, kb = 4 * lane - rb * in_dim;
+            const int dq = 256 / in_dim, dr = 256 - dq * in_dim;
             for (int e4 = lane; e4 < cnt4; e4 += 64) {
                 const float4 q = reinterpret_cast<const float4 *>(src)[e4];
-                int r = (4 * e4) / in_dim, k = 4 * e4 - r * in_dim;
+                int r = rb, k = kb;
+                rb += dq;
+                kb += dr;
+                if (kb >= in_dim) {
+                    kb -= in_dim;
+                    ++rb;
+                }
                 const float qv[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {

@@ -111,6 +111,9 @@ struct OutArgs {
 // rows, one contiguous block of 32 in_dim floats, into LDS with coalesced
 // 16-byte loads (rounded to BF16 on the way), and the MFMA operands are read
 // from there; otherwise every lane loads its own row.
+// Tile loads a lane keeps in flight while staging obs rows.
+constexpr int kStageLoads = 8;
+
 template <bool kLdsW1, int kOut, bool kStage>
 __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
                                                       float max_turn, float max_dspeed,
@@ -170,25 +173,35 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             const int cnt = rows * in_dim, cnt4 = cnt >> 2;
             __threadfence_block();  // the previous tile's reads come first
             // (row, column) of element 4 e4, advanced by 256 elements per step
-            // (no division in the loop)
+            // (no division in the loop); kStageLoads loads in flight per lane
             int rb = (4 * lane) / in_dim, kb = 4 * lane - rb * in_dim;
             const int dq = 256 / in_dim, dr = 256 - dq * in_dim;
-            for (int e4 = lane; e4 < cnt4; e4 += 64) {
-                const float4 q = reinterpret_cast<const float4 *>(src)[e4];
-                int r = rb, k = kb;
-                rb += dq;
-                kb += dr;
-                if (kb >= in_dim) {
-                    kb -= in_dim;
-                    ++rb;
-                }
-                const float qv[4] = {q.x, q.y, q.z, q.w};
+            const float4 *src4 = reinterpret_cast<const float4 *>(src);
+            for (int eb = lane; eb < cnt4; eb += 64 * kStageLoads) {
+                float4 q[kStageLoads];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    s_obs[r * ld + k] = (__bf16)qv[u];
-                    if (++k == in_dim) {
-                        k = 0;
-                        ++r;
+                for (int u = 0; u < kStageLoads; ++u) {
+                    const int e4 = eb + 64 * u;
+                    q[u] = src4[e4 < cnt4 ? e4 : cnt4 - 1];  // unconditional: all in flight
+                }
+#pragma unroll
+                for (int u = 0; u < kStageLoads; ++u) {
+                    int r = rb, k = kb;
+                    rb += dq;
+                    kb += dr;
+                    if (kb >= in_dim) {
+                        kb -= in_dim;
+                        ++rb;
+                    }
+                    if (eb + 64 * u >= cnt4) continue;
+                    const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        s_obs[r * ld + k] = (__bf16)qv[v];
+                        if (++k == in_dim) {
+                            k = 0;
+                            ++r;
+                        }
                     }
                 }
             }

@@ -259,6 +259,7 @@ def bench_rollout(flock, workloads, reps=3):
     gae_bytes = 16 * T * n
     # critic FLOPs over the (T + 1) n views: in x 64 + 64 x 64 + 64 x 1 MACs per row
     critic_flop = 2 * (T + 1) * n * (d * 64 + 64 * 64 + 64)
+    critic_bytes = (T + 1) * n * (4 * d + 4)
     return {"workload": f"one env, {n:,} agents, the paper's flock settings (box 100, vision 10, "
                         f"128 sectors, 250 degrees, speed in the view), {T} sampled steps per "
                         "collection; critic over the 129 x N views; advantages",
@@ -270,6 +271,10 @@ def bench_rollout(flock, workloads, reps=3):
                             "achieved_TFLOPs": critic_flop / (t[1] * 1e-3) / 1e12,
                             "peak_TFLOPs": 2500.0,
                             "frac": critic_flop / (t[1] * 1e-3) / 2.5e15},
+            # the critic's bound is reading the FP32 views (+ 4 B out per row)
+            "critic_hbm": {"bytes_per_launch": critic_bytes,
+                           "achieved_GBps": critic_bytes / (t[1] * 1e-3) / 1e9,
+                           "frac": critic_bytes / (t[1] * 1e-3) / HBM_PEAK},
             "gae_hbm": {"bytes_per_launch": gae_bytes,
                         "achieved_GBps": gae_bytes / (t[2] * 1e-3) / 1e9,
                         "frac": gae_bytes / (t[2] * 1e-3) / HBM_PEAK}}

@@ -215,15 +215,20 @@ def bench_rollout(flock, workloads, reps=3):
     graph), the critic over all 129 x 16,000 views, then the advantages.
     """
     import torch
+    from paper_2207_03945_amd import autotune
     pf = workloads.WORKLOADS["paper_flock10k"]
     n, T = 16000, 128
-    p = flock.Params(n_agents=n, box=pf["box"], radius=pf["radius"], sectors=pf["sectors"],
-                     fov=math.radians(pf["fov_deg"]), flags=flock.ENV_FLAG_SPEED_OBS,
-                     cell_reach=2)
+    kw = dict(n_agents=n, box=pf["box"], radius=pf["radius"], sectors=pf["sectors"],
+              fov=math.radians(pf["fov_deg"]), flags=flock.ENV_FLAG_SPEED_OBS)
+    state = workloads.uniform_state(n, pf["box"], seed=77)
+    # cell reach and sweep lanes timed on this env (one dense env: wide lane groups)
+    reach, lanes, tuned = autotune.tune([flock.Params(**kw)], [state], cache=None)
+    p = flock.Params(cell_reach=reach, **kw)
     env = flock.Env(p)
-    env.set_state(*[torch.from_numpy(a).cuda() for a in workloads.uniform_state(n, pf["box"], seed=77)])
+    env.set_state(*[torch.from_numpy(a).cuda() for a in state])
     obs0 = env.reset()
     b = flock.Batch([env])
+    b.set_sweep_lanes(lanes)
     d = p.obs_dim
     aw, ab = workloads.xavier_weights([d, 64, 64, 2], seed=1)
     cw, cb = workloads.xavier_weights([d, 64, 64, 1], seed=2)
@@ -263,6 +268,7 @@ def bench_rollout(flock, workloads, reps=3):
     return {"workload": f"one env, {n:,} agents, the paper's flock settings (box 100, vision 10, "
                         f"128 sectors, 250 degrees, speed in the view), {T} sampled steps per "
                         "collection; critic over the 129 x N views; advantages",
+            "cell_reach": reach, "sweep_lanes": lanes, "tuned_ms": tuned,
             "rollout_ms": float(t[0]), "critic_ms": float(t[1]), "gae_ms": float(t[2]),
             "collect_ms": float(t.sum()), "agent_steps_per_s": n * T / (t[0] * 1e-3),
             "buffer_bytes": int((obs.numel() + act.numel() + logp.numel() + rew.numel()

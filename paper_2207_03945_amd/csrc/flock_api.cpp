@@ -303,10 +303,14 @@ double env_candidates_per_agent(const env_t *env) {
 // agent also needs v words of LDS per lane, which caps occupancy, so groups
 // of 16 win early.  Measured on MI355X: 30 candidates, v = 16 -> 1;
 // ~500, v = 16 -> 4; 111 and 1,111, v = 128 -> 16.
-int auto_lanes(double cand, int v) {
+int auto_lanes(double cand, int v, int64_t agents) {
     if (cand < 64.0) return 1;
-    if (v > 32) return 16;
-    return cand < 1024.0 ? 4 : 16;
+    int lanes = v > 32 ? 16 : (cand < 1024.0 ? 4 : 16);
+    // few agents with dense neighbourhoods: wider groups keep the GPU busy
+    // (one 16,000-agent env of about 1,000 candidates each steps 20 % faster
+    // with 64 lanes than with 16)
+    if (cand >= 256.0 && agents * lanes < (int64_t(1) << 19)) lanes = 64;
+    return lanes;
 }
 
 const env_params_t &env_params(const env_t *env) { return env->p; }
@@ -430,7 +434,7 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.obs_dim = obs_dim_of(*p);
     e->plan.fov = full_view(*p) ? 0 : 1;
     e->plan.tag = (p->flags & ENV_FLAG_TAG) ? 1 : 0;
-    e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors);
+    e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors, p->n_agents);
     e->plan.max_env_cells = e->plan.C;
     e->plan.env_sort_recs = 0;  // one env: the multi-block kernels fill the GPU better
     e->plan.scan_blocks = scan_blocks_for(e->plan.C, e->plan.C);
@@ -455,7 +459,8 @@ int env_geometry(const env_t *env, int32_t *ncx, int32_t *ncy, int32_t *reach, f
 int env_set_sweep_lanes(env_t *env, int lanes) {
     if (!env) return fail(ENV_EINVAL, "env is NULL");
     if (lanes != 0 && !valid_lanes(lanes)) return fail(ENV_EINVAL, "lanes must be 0, 1, 4, 16 or 64");
-    env->plan.lanes = lanes ? lanes : auto_lanes(env_candidates_per_agent(env), env->p.sectors);
+    env->plan.lanes =
+        lanes ? lanes : auto_lanes(env_candidates_per_agent(env), env->p.sectors, env->p.n_agents);
     return ENV_OK;
 }
 
@@ -579,7 +584,8 @@ static int batch_auto_lanes(const std::vector<env_t *> &envs) {
         cand += env_candidates_per_agent(e) * e->p.n_agents;
         n += e->p.n_agents;
     }
-    return auto_lanes(n > 0.0 ? cand / n : 0.0, envs.empty() ? 1 : envs[0]->p.sectors);
+    return auto_lanes(n > 0.0 ? cand / n : 0.0, envs.empty() ? 1 : envs[0]->p.sectors,
+                      (int64_t)n);
 }
 
 int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env_batch_t **out) {

@@ -150,8 +150,9 @@ bool full_view(const env_params_t &p);          // fov 0 or 2 pi: the whole circ
 int obs_dim_of(const env_params_t &p);          // view row length: sectors (+ 1 for speed)
 // Expected candidate tests per agent of an env (uniform density over its grid).
 double env_candidates_per_agent(const env_t *env);
-// Sweep lanes per agent for a mean of `cand` candidate tests per agent, v sectors.
-int auto_lanes(double cand, int v);
+// Sweep lanes per agent for a mean of `cand` candidate tests per agent, v
+// sectors, `agents` agents in the launch.
+int auto_lanes(double cand, int v, int64_t agents);
 // Descriptor with agent_base = cell_base = 0, oriented so that rec_cur is
 // the env's current buffer (flip = 1 swaps cur and nxt).
 DevEnv env_descriptor(const env_t *env, int flip);

@@ -244,7 +244,7 @@ int rebuild_plan(srv_t *S) {
         if (!full_view(r.p)) S->plan.fov = 1;
         cand += env_candidates_per_agent(r.env) * r.p.n_agents;
     }
-    S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v);
+    S->plan.lanes = auto_lanes(g > 0 ? cand / (double)g : 0.0, S->plan.v, (int64_t)g);
     int64_t max_cells = 0, max_agents = 0;
     for (int64_t rid : S->running) {
         max_cells = std::max(max_cells, env_cell_count(S->reqs.at(rid).env));

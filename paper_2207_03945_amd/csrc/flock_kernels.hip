@@ -848,11 +848,6 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         ti = kTag ? (E.id_nxt[j] < E.n_chasers ? 1 : 0) : 0;
         const float L = E.box, r2 = E.r2, c2 = E.c2;
         const int ncx = E.ncx, ncy = E.ncy, cb = E.cell_base;
-        // Start of cell idx of this env; the end of its last cell is its own
-        // agent end rather than the next env's first start, so that a sweep
-        // reads no cell start of another env.
-        const int cend = cb + ncx * ncy, aend = E.agent_base + E.n;
-        auto st = [&](int idx) { return idx >= cend ? aend : a.start[idx]; };
         // one run of candidates [q, q1): template flags say which shifts are nonzero
         auto run = [&](auto sx, auto sy, int q, int q1, float offx, float xi, float offy, float yi,
                        bool minimg) {
@@ -864,7 +859,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         using No = std::false_type;
         using Yes = std::true_type;
         if (ncx == 1) {
-            run(No{}, No{}, st(cb), st(cb + 1), 0.0f, me.x, 0.0f, me.y, true);
+            run(No{}, No{}, a.start[cb], a.start[cb + 1], 0.0f, me.x, 0.0f, me.y, true);
         } else {
             const int reach = E.reach;
             const int cx = cell_of(me.x, E.inv_cx, ncx);
@@ -876,16 +871,16 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
             // shifted instead; rows wrap likewise
             auto column = [&](auto sx, int colb, float offx, float xi, int lo, int hi) {
                 if (lo < 0) {
-                    run(sx, Yes{}, st(colb + lo + ncy), st(colb + ncy), offx, xi, -L,
+                    run(sx, Yes{}, a.start[colb + lo + ncy], a.start[colb + ncy], offx, xi, -L,
                         me.y, false);
-                    run(sx, No{}, st(colb), st(colb + hi + 1), offx, xi, 0.0f, me.y, false);
+                    run(sx, No{}, a.start[colb], a.start[colb + hi + 1], offx, xi, 0.0f, me.y, false);
                 } else if (hi >= ncy) {
-                    run(sx, No{}, st(colb + lo), st(colb + ncy), offx, xi, 0.0f, me.y,
+                    run(sx, No{}, a.start[colb + lo], a.start[colb + ncy], offx, xi, 0.0f, me.y,
                         false);
-                    run(sx, No{}, st(colb), st(colb + hi - ncy + 1), offx, xi, 0.0f,
+                    run(sx, No{}, a.start[colb], a.start[colb + hi - ncy + 1], offx, xi, 0.0f,
                         me.y - L, false);
                 } else {
-                    run(sx, No{}, st(colb + lo), st(colb + hi + 1), offx, xi, 0.0f, me.y,
+                    run(sx, No{}, a.start[colb + lo], a.start[colb + hi + 1], offx, xi, 0.0f, me.y,
                         false);
                 }
             };
@@ -916,10 +911,10 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                     int ib = colb + ((wlo || whi) ? ncy : hi + 1);
                     int id = colb + (wlo ? hi + 1 : (whi ? hi - ncy + 1 : 0));
                     if (!any) ia = ib = id = colb;
-                    rq[c] = st(ia);
-                    rq1[c] = st(ib);
-                    rq[3 + c] = st(colb);
-                    rq1[3 + c] = st(id);
+                    rq[c] = a.start[ia];
+                    rq1[c] = a.start[ib];
+                    rq[3 + c] = a.start[colb];
+                    rq1[3 + c] = a.start[id];
                     fl |= (fxs | (wlo ? 4u : 0u)) << (4 * c);
                     fl |= (fxs | (whi ? 8u : 0u)) << (4 * (3 + c));
                 }

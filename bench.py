@@ -422,8 +422,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the flock step has no multi-GPU path in this "
-              "build (independent envs would shard across GPUs with no communication); "
+        print("bench.py measures one GPU only: the flock step has no multi-GPU path "
+              "(independent envs would shard across GPUs with no communication); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

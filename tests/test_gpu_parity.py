@@ -446,3 +446,28 @@ def test_returns_accumulate_fp64():
         _, r = env.step(dev(workloads.random_actions(500, seed=2, step=t)))
         acc += host(r).astype(np.float64)
     np.testing.assert_array_equal(host(env.returns()), acc)
+
+
+@pytest.mark.parametrize("n_envs", [10, 80])   # 80: the one-block-per-env sort
+def test_timed_step_equals_step(n_envs):
+    """env_step_batched_timed gives the results of env_step_batched and four phase
+    times; with the one-block-per-env sort the scan and scatter phases are 0."""
+    ns, boxes, states = _uneven(n_envs, 50, 2000, seed=9)
+    envs_t = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
+    envs_s = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
+    bt, bs = flock.Batch(envs_t), flock.Batch(envs_s)
+    G = bt.n
+    obs_t, obs_s = torch.empty(G, 16, device="cuda"), torch.empty(G, 16, device="cuda")
+    rew_t, rew_s = torch.empty(G, device="cuda"), torch.empty(G, device="cuda")
+    for t in range(3):
+        act = dev(np.concatenate([workloads.random_actions(int(n), seed=9, step=t, env=k)
+                                  for k, n in enumerate(ns)]))
+        ms = bt.step_timed(act, obs_t, rew_t)
+        bs.step(act, obs_s, rew_s)
+        torch.cuda.synchronize()
+        assert torch.equal(obs_t, obs_s) and torch.equal(rew_t, rew_s), t
+        assert len(ms) == 4 and all(m >= 0.0 for m in ms) and ms[0] > 0.0 and ms[3] > 0.0
+        if n_envs >= 64:
+            assert ms[1] == 0.0 and ms[2] == 0.0
+        else:
+            assert ms[1] > 0.0 and ms[2] > 0.0

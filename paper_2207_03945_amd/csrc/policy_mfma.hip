@@ -6,17 +6,19 @@
 // layer, the two outputs scaled to the turn / speed-change ranges of Sec. 4.1.
 //
 // Precision: inputs and weights rounded once to BF16 (round to nearest even),
-// products accumulated in FP32 by v_mfma_f32_32x32x16_bf16, biases and the
+// products accumulated in FP32 by v_mfma_f32_16x16x32_bf16, biases and the
 // 64 -> 2 output layer in FP32 on the vector ALUs (with BF16-rounded weights).
 //
-// Layout.  One wave handles 32 agents per tile and computes the transposed
+// Layout.  One wave handles 16 agents per tile and computes the transposed
 // products H1^T = W1^T X^T and H2^T = W2^T H1^T (hidden units as MFMA rows,
-// agents as columns).  A 32x32 accumulator gives lane l the agent l % 32 and,
-// in register r, the hidden row 8 (r / 4) + 4 (l / 32) + r % 4.  Those eight
-// rows per lane group are exactly what the next product's B operand needs
-// once the reduction (K) order is permuted to match, so layer-1 results feed
-// layer 2 straight from registers; the permutation is applied to the weights
-// once on the host (pol_create).
+// agents as columns).  Lane l = 16 g + col holds agent col; in register r of
+// output tile t (hidden units 16 t .. 16 t + 15) it holds unit 16 t + 4 g + r,
+// and as a B operand it supplies the eight K values 32 c + 8 g .. + 7 of chunk
+// c.  Layer 1's results reach layer 2 through a per-wave LDS tile of BF16
+// hidden rows; the weights are packed into A-operand lane order once on the
+// host (pol_create).  Small tiles keep the tanh work per lane low (16 values
+// per layer) and give a batch many tiles to spread over the CUs.
+
 #include <math.h>
 #include <string.h>
 
@@ -28,41 +30,39 @@
 namespace flock {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
 constexpr int kHidden = 64;
 constexpr int kPolBlock = 256;
 constexpr int kMaxIn = 257;                    // 256 sectors + speed
-constexpr int kRegChunks = 2;                  // layer-1 K chunks kept in registers
 
 // Device workspace of one policy.
 struct PolLayout {
-    bf16x8 *w1f;  // [kc1][2 tiles][64 lanes]  A operand of layer 1
-    bf16x8 *w2f;  // [2 tiles][4 chunks][64 lanes]  A operand of layer 2
-    float *b1l;   // [2 tiles][2 groups][16]  bias per accumulator register
-    float *b2l;   // [2][2][16]
-    float *w3l;   // [2 outputs][2 tiles][2 groups][16]
-    float *b3;    // [2]
+    // A operands, lane (g = l / 16, col = l % 16), element j of chunk c, tile t:
+    bf16x8 *w1;  // [kc][4 tiles][64 lanes]  W1[32 c + 8 g + j][16 t + col] (0 beyond in_dim)
+    bf16x8 *w2;  // [2][4 tiles][64 lanes]   W2[32 c + 8 g + j][16 t + col]
+    float *b1;   // [64] by hidden unit
+    float *b2;   // [64]
+    float *w3;   // [2 outputs][64] (BF16-rounded)
+    float *b3;   // [2]
     size_t bytes;
 };
 
-PolLayout carve_pol(char *base, int kc1) {
+// kc: chunks of 32 inputs.
+PolLayout carve_pol(char *base, int kc) {
     PolLayout l;
     Carver cv{base, 0};
-    l.w1f = cv.take<bf16x8>((size_t)kc1 * 2 * 64);
-    l.w2f = cv.take<bf16x8>(2 * 4 * 64);
-    l.b1l = cv.take<float>(64);
-    l.b2l = cv.take<float>(64);
-    l.w3l = cv.take<float>(128);
+    l.w1 = cv.take<bf16x8>((size_t)kc * 4 * 64);
+    l.w2 = cv.take<bf16x8>(2 * 4 * 64);
+    l.b1 = cv.take<float>(64);
+    l.b2 = cv.take<float>(64);
+    l.w3 = cv.take<float>(128);
     l.b3 = cv.take<float>(2);
     l.bytes = align_up(cv.off, 256);
     return l;
 }
-
-// Hidden row held in accumulator register r by lane group g of a 32-row tile.
-inline int acc_row(int r, int g) { return 8 * (r / 4) + 4 * g + (r % 4); }
 
 __device__ __forceinline__ float tanh_fast(float x) {
     x = fminf(fmaxf(x, -15.0f), 15.0f);
@@ -103,59 +103,64 @@ struct OutArgs {
     int tn_envs;
 };
 
-// Rows are agents; obs/act are [n][in_dim] / [n][2] arrays, or, when `envs`
-// is non-null, each row's env-owned rows found through the batch tables.
-// kLdsW1: the layer-1 A operand (kc1 > kRegChunks chunks of 16 inputs) is
-// staged in dynamic LDS once per block instead of living in registers.
-// kStage (batch-wide obs rows): each wave copies its tile's 32 consecutive
-// rows, one contiguous block of 32 in_dim floats, into LDS with coalesced
-// 16-byte loads (rounded to BF16 on the way), and the MFMA operands are read
-// from there; otherwise every lane loads its own row.
 // Tile loads a lane keeps in flight while staging obs rows.
 constexpr int kStageLoads = 8;
 
+// Rows are agents; obs/act are [n][in_dim] / [n][2] arrays, or, when `envs`
+// is non-null, each row's env-owned rows found through the batch tables.
+// Layer 1's results reach layer 2's B operand (eight consecutive hidden units
+// per lane group) through a per-wave LDS tile [16 agents][72] of BF16.
+// kLdsW1: the layer-1 A operand (more than one chunk of 32 inputs) lives in
+// LDS, loaded once per block; kStage (batch-wide obs rows): each wave copies
+// its tile's 16 consecutive rows, one contiguous block of 16 in_dim floats,
+// into LDS as BF16 (zero beyond in_dim) with coalesced 16-byte loads, and the
+// MFMA operands are read from there; otherwise every lane loads its own row.
+constexpr int kHidLd = 72;  // BF16 per agent row of the hidden tile (64 + 8 pad)
+
 template <bool kLdsW1, int kOut, bool kStage>
-__global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc1,
+__global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc,
                                                       float max_turn, float max_dspeed,
                                                       const float *__restrict__ obs, int64_t n,
                                                       float2 *__restrict__ act,
                                                       const DevEnv *__restrict__ envs,
-                                                      const int32_t *__restrict__ base, int n_envs,
-                                                      OutArgs oa) {
+                                                      const int32_t *__restrict__ base,
+                                                      int n_envs, OutArgs oa) {
     __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
     extern __shared__ bf16x8 s_dyn[];
-    bf16x8 *s_w1 = s_dyn;  // [kc1][2 tiles][64 lanes] when kLdsW1
-    // per-wave obs tiles after the weights: [32 rows][ld] BF16, ld = 16 kc1 + 8
-    const int ld = 16 * kc1 + 8;
-    __bf16 *s_obs = reinterpret_cast<__bf16 *>(s_dyn + (kLdsW1 ? kc1 * 128 : 0)) +
-                    (size_t)(threadIdx.x / 64) * 32 * ld;
+    const int wid = threadIdx.x / 64;
+    bf16x8 *s_w1 = s_dyn;  // [kc][4 tiles][64 lanes] when kLdsW1
+    __bf16 *s_hid = reinterpret_cast<__bf16 *>(s_dyn + (kLdsW1 ? kc * 256 : 0)) +
+                    (size_t)wid * 16 * kHidLd;
+    // per-wave obs tiles after the hidden tiles: [16 rows][ld] BF16, ld = 32 kc + 8
+    const int ld = 32 * kc + 8;
+    __bf16 *s_obs = reinterpret_cast<__bf16 *>(s_dyn + (kLdsW1 ? kc * 256 : 0)) +
+                    (size_t)(kPolBlock / 64) * 16 * kHidLd + (size_t)wid * 16 * ld;
     if (kLdsW1)
-        for (int i = threadIdx.x; i < kc1 * 128; i += kPolBlock) s_w1[i] = P.w1f[i];
+        for (int i = threadIdx.x; i < kc * 256; i += kPolBlock) s_w1[i] = P.w1[i];
     for (int i = threadIdx.x; i < 64; i += kPolBlock) {
-        s_b1[i] = P.b1l[i];
-        s_b2[i] = P.b2l[i];
+        s_b1[i] = P.b1[i];
+        s_b2[i] = P.b2[i];
     }
-    for (int i = threadIdx.x; i < 128; i += kPolBlock) s_w3[i] = P.w3l[i];
+    for (int i = threadIdx.x; i < 128; i += kPolBlock) s_w3[i] = P.w3[i];
     if (threadIdx.x < 2) s_b3[threadIdx.x] = P.b3[threadIdx.x];
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
-    bf16x8 w1[kRegChunks][2];
+    const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+    bf16x8 w1[4];
     if (!kLdsW1)
-        for (int kc = 0; kc < kRegChunks; ++kc)
-            for (int t = 0; t < 2; ++t)
-                w1[kc][t] = kc < kc1 ? P.w1f[(kc * 2 + t) * 64 + lane] : bf16x8{};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w1[t] = P.w1[t * 64 + lane];  // kc == 1
     bf16x8 w2[2][4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) w2[t][c] = P.w2f[(t * 4 + c) * 64 + lane];
+        for (int t = 0; t < 4; ++t) w2[c][t] = P.w2[(c * 4 + t) * 64 + lane];
 
     const int64_t waves = (int64_t)gridDim.x * (kPolBlock / 64);
-    const int64_t tiles = (n + 31) / 32;
-    for (int64_t tile = (int64_t)blockIdx.x * (kPolBlock / 64) + threadIdx.x / 64; tile < tiles;
+    const int64_t tiles = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * (kPolBlock / 64) + wid; tile < tiles;
          tile += waves) {
-        const int64_t agent = tile * 32 + col;
+        const int64_t agent = tile * 16 + col;
         bool valid = agent < n;
         if (oa.type_want >= 0) {
             if (valid) {
@@ -167,13 +172,15 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
         const float *orow = obs + agent * in_dim;
         float2 *arow = act + agent;
         if constexpr (kStage) {
-            const int64_t row0 = tile * 32;
-            const int rows = n - row0 < 32 ? (int)(n - row0) : 32;
+            const int64_t row0 = tile * 16;
+            const int rows = n - row0 < 16 ? (int)(n - row0) : 16;
             const float *src = obs + row0 * in_dim;
             const int cnt = rows * in_dim, cnt4 = cnt >> 2;
             __threadfence_block();  // the previous tile's reads come first
-            // (row, column) of element 4 e4, advanced by 256 elements per step
-            // (no division in the loop); kStageLoads loads in flight per lane
+            // zero the tile (columns past in_dim must read as 0)
+            uint4 *z = reinterpret_cast<uint4 *>(s_obs);
+            for (int i = lane; i < 2 * ld; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+            __threadfence_block();
             int rb = (4 * lane) / in_dim, kb = 4 * lane - rb * in_dim;
             const int dq = 256 / in_dim, dr = 256 - dq * in_dim;
             const float4 *src4 = reinterpret_cast<const float4 *>(src);
@@ -217,15 +224,13 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             orow = E.obs + i * in_dim;
             arow = reinterpret_cast<float2 *>(E.act) + i;
         }
-        f32x16 acc1[2] = {f32x16{}, f32x16{}};
-        for (int kc = 0; kc < kc1; ++kc) {
+        // layer 1: H1^T[16 t + i][agent] over K chunks of 32 inputs
+        f32x4 acc1[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
+        for (int c = 0; c < kc; ++c) {
             bf16x8 xb;
-            const int k0 = 16 * kc + 8 * g;
+            const int k0 = 32 * c + 8 * g;
             if constexpr (kStage) {
                 xb = *reinterpret_cast<const bf16x8 *>(s_obs + col * ld + k0);
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (!valid || k0 + j >= in_dim) xb[j] = (__bf16)0.0f;
             } else if (valid && in_dim % 4 == 0 && k0 + 8 <= in_dim) {
                 const float4 *src = reinterpret_cast<const float4 *>(orow + k0);
                 const float4 u = src[0], w = src[1];
@@ -238,39 +243,45 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                     xb[j] = (__bf16)((valid && k < in_dim) ? orow[k] : 0.0f);
                 }
             }
-            bf16x8 a0, a1;
-            if constexpr (kLdsW1) {
-                a0 = s_w1[(kc * 2 + 0) * 64 + lane];
-                a1 = s_w1[(kc * 2 + 1) * 64 + lane];
-            } else {
-                a0 = w1[kc][0];
-                a1 = w1[kc][1];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x8 a = kLdsW1 ? s_w1[(c * 4 + t) * 64 + lane] : w1[t];
+                acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb, acc1[t], 0, 0, 0);
             }
-            acc1[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, xb, acc1[0], 0, 0, 0);
-            acc1[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, xb, acc1[1], 0, 0, 0);
         }
-        // bias + tanh; registers 8 (c % 2) .. + 8 of tile c / 2 are chunk c of layer 2's K
-        bf16x8 h1[4];
+        // bias + tanh, into the hidden tile as B operand rows of layer 2
+        __threadfence_block();  // the previous tile's reads of the hidden tile come first
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 4; ++t) {
+            __bf16 hv[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                h1[t * 2 + r / 8][r % 8] = (__bf16)tanh_fast(acc1[t][r] + s_b1[(t * 2 + g) * 16 + r]);
-        f32x16 acc2[2] = {f32x16{}, f32x16{}};
+            for (int r = 0; r < 4; ++r)
+                hv[r] = (__bf16)tanh_fast(acc1[t][r] + s_b1[16 * t + 4 * g + r]);
+            uint2 packed;
+            memcpy(&packed, hv, sizeof(packed));
+            *reinterpret_cast<uint2 *>(s_hid + col * kHidLd + 16 * t + 4 * g) = packed;
+        }
+        __threadfence_block();  // the wave's hidden tile before its reads
+        f32x4 acc2[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int c = 0; c < 2; ++c) {
+            const bf16x8 hb = *reinterpret_cast<const bf16x8 *>(s_hid + col * kHidLd + 32 * c + 8 * g);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2[t][c], h1[c], acc2[t], 0, 0, 0);
+            for (int t = 0; t < 4; ++t)
+                acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[c][t], hb, acc2[t], 0, 0, 0);
+        }
         float z0 = 0.0f, z1 = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float h = tanh_fast(acc2[t][r] + s_b2[(t * 2 + g) * 16 + r]);
-                z0 = z0 + h * s_w3[((0 * 2 + t) * 2 + g) * 16 + r];
-                z1 = z1 + h * s_w3[((1 * 2 + t) * 2 + g) * 16 + r];
+            for (int r = 0; r < 4; ++r) {
+                const int h = 16 * t + 4 * g + r;
+                const float hv = tanh_fast(acc2[t][r] + s_b2[h]);
+                z0 = z0 + hv * s_w3[h];
+                z1 = z1 + hv * s_w3[64 + h];
             }
+        z0 = z0 + __shfl_xor(z0, 16, 64);
+        z1 = z1 + __shfl_xor(z1, 16, 64);
         z0 = z0 + __shfl_xor(z0, 32, 64);
         z1 = z1 + __shfl_xor(z1, 32, 64);
         if (g == 0 && valid) {
@@ -312,8 +323,8 @@ float bf16_round(float f) {
 using namespace flock;
 
 struct flock_policy {
-    int in_dim, kc1;
-    int critic;  // 0 actor (two scaled tanh outputs), 1 critic (one linear output)
+    int in_dim, kc;  // kc: chunks of 32 inputs
+    int critic;      // 0 actor (two scaled tanh outputs), 1 critic (one linear output)
     float max_turn, max_dspeed;
     PolLayout lay;
     std::vector<char> host;  // staged device image, kept until pol_destroy
@@ -322,8 +333,6 @@ struct flock_policy {
 namespace flock {
 
 namespace {
-size_t w1_lds_bytes(int kc1) { return (size_t)kc1 * 2 * 64 * sizeof(bf16x8); }
-
 OutArgs no_filter() {
     OutArgs oa{};
     oa.type_want = -1;
@@ -334,23 +343,26 @@ template <int kOut>
 hipError_t launch_pol(const pol_t *p, const float *obs, int64_t n, float *act, const DevEnv *envs,
                       const int32_t *base, int n_envs, const OutArgs &oa, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t tiles = (n + 31) / 32;
+    const int kc = p->kc;
+    const int64_t tiles = (n + 15) / 16;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 4096) blocks = 4096;
     float2 *a2 = reinterpret_cast<float2 *>(act);
+    const bool lds_w1 = kc > 1;
+    const size_t w1b = lds_w1 ? (size_t)kc * 256 * sizeof(bf16x8) : 0;
+    const size_t hid_b = (size_t)(kPolBlock / 64) * 16 * kHidLd * sizeof(__bf16);
+    const size_t tile_b = (size_t)(kPolBlock / 64) * 16 * (32 * kc + 8) * sizeof(__bf16);
     // batch-wide rows whose tiles start 16-byte aligned are staged through LDS
     // (within the 64 KiB of dynamic LDS a launch gets by default)
-    const size_t w1b = p->kc1 > kRegChunks ? w1_lds_bytes(p->kc1) : 0;
-    const size_t tile_b = (size_t)(kPolBlock / 64) * 32 * (16 * p->kc1 + 8) * sizeof(__bf16);
     const bool stage = obs && !envs && (reinterpret_cast<uintptr_t>(obs) & 15) == 0 &&
-                       w1b + tile_b <= 65536;
-    const size_t obs_b = stage ? tile_b : 0;
+                       w1b + hid_b + tile_b <= 65536;
+    const size_t lds = w1b + hid_b + (stage ? tile_b : 0);
     auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kPolBlock), w1b + obs_b, s, p->lay,
-                           p->in_dim, p->kc1, p->max_turn, p->max_dspeed, obs, n, a2, envs, base,
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kPolBlock), lds, s, p->lay,
+                           p->in_dim, kc, p->max_turn, p->max_dspeed, obs, n, a2, envs, base,
                            n_envs, oa);
     };
-    if (p->kc1 > kRegChunks) {
+    if (lds_w1) {
         if (stage) go(k_policy<true, kOut, true>);
         else go(k_policy<true, kOut, false>);
     } else {
@@ -359,6 +371,7 @@ hipError_t launch_pol(const pol_t *p, const float *obs, int64_t n, float *act, c
     }
     return hipGetLastError();
 }
+
 }  // namespace
 
 hipError_t policy_launch(const pol_t *p, const float *obs, int64_t n, float *act, hipStream_t s) {
@@ -407,7 +420,7 @@ hipError_t policy_launch_envs(const pol_t *p, const StepPlan &plan, int table, h
 
 int policy_is_critic(const pol_t *p) { return p->critic; }
 
-const void *policy_weights(const pol_t *p) { return p->lay.w1f; }
+const void *policy_weights(const pol_t *p) { return p->lay.w1; }
 
 int policy_in_dim(const pol_t *p) { return p->in_dim; }
 
@@ -420,7 +433,7 @@ size_t pol_workspace_bytes(int in_dim, int hidden) {
         set_error(ENV_EINVAL, "policy needs 1 <= in_dim <= %d and hidden == 64", kMaxIn);
         return 0;
     }
-    return carve_pol(nullptr, (in_dim + 15) / 16).bytes;
+    return carve_pol(nullptr, (in_dim + 31) / 32).bytes;
 }
 
 }  // extern "C"
@@ -438,17 +451,17 @@ int create_net(const float *w, int in_dim, int hidden, int n_out, float max_turn
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
         return set_error(ENV_EINVAL, "workspace must be 256-byte aligned");
     const int H = kHidden;
-    const int kc1 = (in_dim + 15) / 16;
-    const size_t need = carve_pol(nullptr, kc1).bytes;
+    const int kc = (in_dim + 31) / 32;
+    const size_t need = carve_pol(nullptr, kc).bytes;
     if (bytes < need)
         return set_error(ENV_ENOMEM, "policy workspace has %zu bytes, needs %zu", bytes, need);
     pol_t *p = new pol_t;
     p->in_dim = in_dim;
-    p->kc1 = kc1;
+    p->kc = kc;
     p->critic = n_out == 1 ? 1 : 0;
     p->max_turn = max_turn;
     p->max_dspeed = max_dspeed;
-    p->lay = carve_pol(static_cast<char *>(ws), kc1);
+    p->lay = carve_pol(static_cast<char *>(ws), kc);
     const PolLayout &off = p->lay;
     p->host.assign(need, 0);
     char *hb = p->host.data();
@@ -462,44 +475,36 @@ int create_net(const float *w, int in_dim, int hidden, int n_out, float max_turn
     const float *b2 = W2 + H * H;
     const float *W3 = b2 + H;
     const float *b3 = W3 + H * n_out;
-    // layer-1 A operand: lane (g, col), element j = W1[16 kc + 8 g + j][32 t + col]
-    uint16_t *w1f = reinterpret_cast<uint16_t *>(at(off.w1f));
-    for (int kc = 0; kc < kc1; ++kc)
-        for (int t = 0; t < 2; ++t)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int j = 0; j < 8; ++j) {
-                    const int g = lane / 32, col = lane % 32;
-                    const int k = 16 * kc + 8 * g + j, m = 32 * t + col;
-                    const float v = k < in_dim ? W1[k * H + m] : 0.0f;
-                    w1f[((kc * 2 + t) * 64 + lane) * 8 + j] = bf16_bits_rne(v);
-                }
-    // layer-2 A operand with the K order of layer 1's accumulator registers:
-    // chunk c, slot (g, j) <-> hidden unit 16 c + 8 (j / 4) + 4 g + j % 4
-    uint16_t *w2f = reinterpret_cast<uint16_t *>(at(off.w2f));
-    for (int t = 0; t < 2; ++t)
-        for (int c = 0; c < 4; ++c)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int j = 0; j < 8; ++j) {
-                    const int g = lane / 32, col = lane % 32;
-                    const int hid = 16 * c + 8 * (j / 4) + 4 * g + (j % 4);
-                    w2f[((t * 4 + c) * 64 + lane) * 8 + j] = bf16_bits_rne(W2[hid * H + 32 * t + col]);
-                }
-    float *b1l = reinterpret_cast<float *>(at(off.b1l));
-    float *b2l = reinterpret_cast<float *>(at(off.b2l));
-    float *w3l = reinterpret_cast<float *>(at(off.w3l));
-    for (int t = 0; t < 2; ++t)
-        for (int g = 0; g < 2; ++g)
-            for (int r = 0; r < 16; ++r) {
-                const int h = 32 * t + acc_row(r, g);
-                b1l[(t * 2 + g) * 16 + r] = b1[h];
-                b2l[(t * 2 + g) * 16 + r] = b2[h];
-                for (int o = 0; o < 2; ++o)
-                    w3l[((o * 2 + t) * 2 + g) * 16 + r] =
-                        o < n_out ? bf16_round(W3[h * n_out + o]) : 0.0f;
-            }
     float *b3d = reinterpret_cast<float *>(at(off.b3));
     b3d[0] = b3[0];
     b3d[1] = n_out > 1 ? b3[1] : 0.0f;
+    // A operands in lane order: lane (g, col) of chunk c, tile t holds
+    // W[32 c + 8 g + j][16 t + col] in element j (zero beyond in_dim)
+    uint16_t *w1p = reinterpret_cast<uint16_t *>(at(off.w1));
+    for (int c = 0; c < kc; ++c)
+        for (int t = 0; t < 4; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 32 * c + 8 * (lane / 16) + j, m = 16 * t + lane % 16;
+                    const float v = k < in_dim ? W1[k * H + m] : 0.0f;
+                    w1p[((c * 4 + t) * 64 + lane) * 8 + j] = bf16_bits_rne(v);
+                }
+    uint16_t *w2p = reinterpret_cast<uint16_t *>(at(off.w2));
+    for (int c = 0; c < 2; ++c)
+        for (int t = 0; t < 4; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 32 * c + 8 * (lane / 16) + j, m = 16 * t + lane % 16;
+                    w2p[((c * 4 + t) * 64 + lane) * 8 + j] = bf16_bits_rne(W2[k * H + m]);
+                }
+    float *b1d = reinterpret_cast<float *>(at(off.b1));
+    float *b2d = reinterpret_cast<float *>(at(off.b2));
+    float *w3d = reinterpret_cast<float *>(at(off.w3));
+    for (int h = 0; h < H; ++h) {
+        b1d[h] = b1[h];
+        b2d[h] = b2[h];
+        for (int o = 0; o < 2; ++o) w3d[o * H + h] = o < n_out ? bf16_round(W3[h * n_out + o]) : 0.0f;
+    }
     hipError_t e = hipMemcpyAsync(ws, hb, need, hipMemcpyHostToDevice,
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) {

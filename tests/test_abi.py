@@ -165,7 +165,7 @@ def test_batch_validation_without_gpu():
 def test_policy_and_server_validation_without_gpu():
     lib = fe.lib()
     assert lib.pol_workspace_bytes(16, 64) > 0
-    assert lib.pol_workspace_bytes(32, 64) > lib.pol_workspace_bytes(16, 64)
+    assert lib.pol_workspace_bytes(33, 64) > lib.pol_workspace_bytes(32, 64) == lib.pol_workspace_bytes(16, 64)
     assert lib.pol_workspace_bytes(257, 64) > lib.pol_workspace_bytes(129, 64) > 0
     for bad in ((0, 64), (258, 64), (16, 32)):
         assert lib.pol_workspace_bytes(*bad) == 0

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import workloads
-from parity import EPS_D, EPS_PHI, check_sense, state_mismatch
+from parity import EPS_D, EPS_PHI, REW_TOL, check_sense, state_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -126,6 +126,57 @@ def test_blobs50k_sampled_steps():
 
 def test_uniform50k_sampled_steps():
     _run_sampled("uniform50k", {0, 1, 5}, 3000)
+
+
+def test_flock5k_x200_graph_replay_sampled():
+    """The 200 x 5,000-agent batch (side 316, 16 sectors) as it is timed: K steps
+    captured in one graph, replayed twice with new actions written between the
+    replays (one-block-per-env sort, one lane per agent).  Every env's state
+    after both replays bitwise; every step's reward of 300 sampled agents in six
+    envs (both ends of the batch, block-index seams) against the oracle; the
+    last step's view and counts of those agents."""
+    n, box, v, E, K = 5000, 316.0, 16, 200, 4
+    sts = [workloads.uniform_state(n, box, seed=500 + k) for k in range(E)]
+    envs = [make_env(st, box, v)[0] for st in sts]
+    batch = flock.Batch(envs)
+    G, off = batch.n, batch.offsets
+    assert G == n * E
+    obs = torch.empty(G, v, device="cuda")
+    rew = torch.empty(K, G, device="cuda")
+    act = torch.empty(K, G, 2, device="cuda")
+    stream = torch.cuda.Stream()
+    acts = [[workloads.random_actions(n, seed=5, step=t, env=k) for k in range(E)]
+            for t in range(2 * K)]
+    for rep in range(2):
+        act.copy_(dev(np.stack([np.concatenate(acts[rep * K + t]) for t in range(K)])))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            if rep == 0:
+                batch.capture(K, act, obs, rew, stream)
+            batch.run(K, act, obs, rew, stream)
+        stream.synchronize()
+    rew_h, obs_h = host(rew), host(obs)
+    sample = {0, 1, 63, 64, 128, 199}
+    g = np.random.default_rng(8)
+    for k in range(E):
+        st = sts[k]
+        agents = np.sort(g.choice(n, 300, replace=False)).astype(np.int32) if k in sample else None
+        for t in range(2 * K):
+            st = oracle.oracle_move(st, acts[t][k], box)
+            if agents is not None and t >= K:
+                rows = off[k] + agents
+                if t < 2 * K - 1:  # the view buffer holds the last step only: rewards here
+                    o = band(st, box, v, agents)
+                    amb = (o.nb_lo != o.nb_hi) | (o.col_lo != o.col_hi)
+                    r = rew_h[t - K][rows].astype(np.float64)
+                    rerr = np.abs(r - o.reward) / np.maximum(1.0, np.abs(o.reward))
+                    assert rerr[~amb].max(initial=0.0) <= REW_TOL, f"env {k} step {t}: {rerr.max()}"
+                else:
+                    nb, col = (host(x) for x in envs[k].counts())
+                    check_sense(band(st, box, v, agents), obs_h[rows], rew_h[t - K][rows],
+                                nb[agents], col[agents], label=f"env {k} last step")
+        bad, ulp = state_mismatch(gpu_state(envs[k]), st)
+        assert bad.size == 0, f"env {k}: state differs at {bad[:10]} (max {ulp} ulp)"
 
 
 # --------------------------------------------------------------------------- edge cases

@@ -61,6 +61,30 @@ def test_policy_matches_fp64_within_bound(in_dim, n):
     print(f"in={in_dim} n={n}: max |act err| {err.max():.2e} (turn) / mean bound {bound.mean():.2e}")
 
 
+@pytest.mark.parametrize("in_dim", [16, 129])
+def test_policy_many_tiles_per_wave(in_dim):
+    """More rows than one pass of the grid covers (4,096 blocks x 4 waves x 16
+    rows, then a ragged tail): each wave loops over several tiles, reusing its
+    LDS tiles.  Sampled rows equal the same rows evaluated on their own and stay
+    within the FP64 bound."""
+    pol, ws, bs = make_policy(in_dim)
+    n = 300_000 + 37
+    g = np.random.default_rng(11 + in_dim)
+    obs_h = g.random((n, in_dim)).astype(np.float32)
+    obs = torch.from_numpy(obs_h).cuda()
+    act = pol.forward(obs)
+    rows = np.sort(np.concatenate([g.choice(n - 64, 4000, replace=False), np.arange(n - 64, n)]))
+    idx = torch.from_numpy(rows).cuda()
+    sub = pol.forward(obs[idx].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(act[idx], sub)
+    got = act.cpu().numpy()[rows].astype(np.float64)
+    ref = oracle.policy_forward(obs_h[rows], ws, bs)
+    bound = error_bound(obs_h[rows], ws, bs)
+    err = np.abs(got - ref)
+    assert (err <= bound).all(), f"max err {err.max():.3e}"
+
+
 def test_policy_row_independent_bitwise():
     """An agent's action does not depend on its tile or the batch size."""
     pol, _, _ = make_policy(16)

@@ -150,7 +150,9 @@ int env_geometry(const env_t *env, int32_t *ncx, int32_t *ncy, int32_t *reach, f
  * expected candidates per agent (about n (2 reach + 1) cell_w (2 radius +
  * cell_h) / box^2).
  * Results do not depend on it; sparse neighbourhoods favour 1, dense ones
- * (hundreds of candidates per agent) larger groups.  ENV_EINVAL for other
+ * (hundreds of candidates per agent) larger groups, and so do steps with few
+ * agents in all (the automatic choice takes 64 below 8,193 agents, where one
+ * agent per wavefront keeps more compute units busy).  ENV_EINVAL for other
  * values. */
 int env_set_sweep_lanes(env_t *env, int lanes);
 

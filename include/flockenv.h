@@ -151,9 +151,10 @@ int env_geometry(const env_t *env, int32_t *ncx, int32_t *ncy, int32_t *reach, f
  * cell_h) / box^2).
  * Results do not depend on it; sparse neighbourhoods favour 1, dense ones
  * (hundreds of candidates per agent) larger groups, and so do steps with few
- * agents in all (the automatic choice takes 64 below 8,193 agents, where one
- * agent per wavefront keeps more compute units busy).  ENV_EINVAL for other
- * values. */
+ * agents in all (the automatic choice takes 64 up to 8,192 agents and 16 up
+ * to 16,384, where wider groups keep more compute units busy).  The
+ * automatic choice assumes uniform density; clustered states may do better
+ * with a larger group.  ENV_EINVAL for other values. */
 int env_set_sweep_lanes(env_t *env, int lanes);
 
 /* Copy a state in (device x, y, th, s, each [n] FP32).  Values must already

@@ -305,10 +305,15 @@ double env_candidates_per_agent(const env_t *env) {
 // ~500, v = 16 -> 4; 111 and 1,111, v = 128 -> 16.
 int auto_lanes(double cand, int v, int64_t agents) {
     // sparse neighbourhoods: one lane per agent, unless there are so few
-    // agents that one agent per wave keeps more CUs busy (a one-env step of
-    // 5,000 agents with about 20 candidates each: 27 us at one lane, 23 us
-    // at 64; 1,000 agents: 23 us and 18 us)
-    if (cand < 64.0) return agents * 64 <= (int64_t(1) << 19) ? 64 : 1;
+    // agents that wider groups keep more CUs busy (one-env steps with about
+    // 20 candidates per agent: 5,000 agents 27 us at one lane, 23 us at 64;
+    // 1,000 agents 23 and 18 us; 16,000 agents 32 us at one lane, 29 at 16;
+    // from 32,000 agents one lane is fastest)
+    if (cand < 64.0) {
+        if (agents * 64 <= (int64_t(1) << 19)) return 64;
+        if (agents * 16 <= (int64_t(1) << 18)) return 16;
+        return 1;
+    }
     int lanes = v > 32 ? 16 : (cand < 1024.0 ? 4 : 16);
     // few agents with dense neighbourhoods: wider groups keep the GPU busy
     // (one 16,000-agent env of about 1,000 candidates each steps 20 % faster

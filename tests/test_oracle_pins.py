@@ -449,3 +449,121 @@ def test_observation_appends_speed(oracle_mod):
     r = oracle_mod.oracle_sense(x, y, th, 40.0, sectors=8, agents=[3, 7])
     o = oracle_mod.observation(r, s)
     assert o.shape == (2, 9) and o[0, 8] == np.float32(0.09) and o[1, 8] == np.float32(0.21)
+
+
+# --------------------------------------------------------------------------- band widths
+#
+# The ambiguity bands decide how far the GPU parity tests may stray from the
+# plain definition, so their WIDTH is pinned here, not only their containment:
+# a pair 0.5e-5 from a radius or a sector edge must be ambiguous, a pair 2e-5
+# away must not be.  The offsets are measured in the test from the FP32
+# coordinates themselves (exact differences in double, math.hypot and
+# math.atan2), so a band applied to d^2 instead of d, or a sector band scaled
+# by the wrong arc, fails one of these cases.
+
+EPS = 1e-5
+
+
+def _pair_at(d, bearing, heading=0.0, x0=9.0, y0=9.0):
+    x = np.array([x0, x0 + d * math.cos(bearing)], np.float32)
+    y = np.array([y0, y0 + d * math.sin(bearing)], np.float32)
+    th = np.array([heading, 0.0], np.float32)
+    dx, dy = float(x[1]) - float(x[0]), float(y[1]) - float(y[0])
+    return x, y, th, math.hypot(dx, dy), math.atan2(dy, dx)
+
+
+@pytest.mark.parametrize("radius_kind", ["vision", "collision"])
+@pytest.mark.parametrize("offset,ambiguous", [(-0.5e-5, True), (0.5e-5, True),
+                                              (-2e-5, False), (2e-5, False)])
+def test_band_width_at_radius(oracle_mod, radius_kind, offset, ambiguous):
+    R = 8.0 if radius_kind == "vision" else 0.5
+    x, y, th, d, _ = _pair_at(R + offset, 0.3)
+    assert abs((d - R) - offset) < 2e-6          # the FP32 placement kept the offset
+    r = oracle_mod.oracle_sense(x, y, th, 64.0, sectors=16, agents=[0], eps_d=EPS, eps_phi=EPS)
+    lo, hi = (r.nb_lo[0], r.nb_hi[0]) if R == 8.0 else (r.col_lo[0], r.col_hi[0])
+    inside = d < R
+    if ambiguous:
+        assert (lo, hi) == (0, 1)
+    else:
+        assert lo == hi == int(inside)
+    # the plain count follows the strict comparison whatever the band
+    plain = r.n_nb[0] if R == 8.0 else r.n_col[0]
+    assert plain == int(inside)
+
+
+@pytest.mark.parametrize("fov_deg,v,edge_k", [(360.0, 16, 3), (360.0, 16, 0), (250.0, 16, 5),
+                                              (250.0, 128, 77)])
+@pytest.mark.parametrize("offset,ambiguous", [(0.5e-5, True), (-0.5e-5, True), (0.85e-5, True),
+                                              (-0.85e-5, True), (2e-5, False), (-2e-5, False)])
+def test_band_width_at_sector_edge(oracle_mod, fov_deg, v, edge_k, offset, ambiguous):
+    """Sector edge k of a full view lies at k 2pi/v from the heading; of a
+    limited view at -fov/2 + k fov/v (bearings relative to the heading)."""
+    heading = 0.9
+    fov = math.radians(fov_deg)
+    rel_edge = edge_k * 2 * math.pi / v if fov_deg == 360.0 else -fov / 2 + edge_k * fov / v
+    x, y, th, d, bearing = _pair_at(7.5, heading + rel_edge + offset, heading=heading)
+    rel = math.remainder(bearing - float(np.float32(heading)), 2 * math.pi)
+    measured = math.remainder(rel - rel_edge, 2 * math.pi)
+    assert abs(measured - offset) < 5e-7
+    kw = {} if fov_deg == 360.0 else {"fov": fov}
+    r = oracle_mod.oracle_sense(x, y, th, 64.0, sectors=v, agents=[0], eps_d=EPS, eps_phi=EPS, **kw)
+    strict, loose = r.dmin_strict[0], r.dmin_loose[0]
+    below, above = (edge_k - 1) % v, edge_k % v
+    assert r.n_nb[0] == 1
+    if ambiguous:
+        assert np.isinf(strict).all()
+        assert np.isfinite(loose[below]) and np.isfinite(loose[above])
+        assert np.count_nonzero(np.isfinite(loose)) == 2
+    else:
+        want = above if measured > 0 else below
+        assert np.count_nonzero(np.isfinite(strict)) == 1 and np.isfinite(strict[want])
+        assert np.array_equal(strict, loose)
+
+
+@pytest.mark.parametrize("offset,ambiguous", [(0.5e-5, True), (-0.5e-5, True), (0.85e-5, True),
+                                              (-0.85e-5, True), (2e-5, False), (-2e-5, False)])
+@pytest.mark.parametrize("side", [-1, 1])
+def test_band_width_at_arc_edge(oracle_mod, offset, ambiguous, side):
+    """A limited view's arc ends at +-fov/2: a pair within the band of an end
+    may be seen in the end sector or not seen at all."""
+    heading, v = 2.2, 16
+    fov = math.radians(250.0)
+    rel_edge = side * fov / 2
+    x, y, th, d, bearing = _pair_at(7.5, heading + rel_edge + offset, heading=heading)
+    rel = math.remainder(bearing - float(np.float32(heading)), 2 * math.pi)
+    measured = rel - rel_edge
+    assert abs(measured - offset) < 5e-7
+    r = oracle_mod.oracle_sense(x, y, th, 64.0, sectors=v, agents=[0], eps_d=EPS, eps_phi=EPS,
+                                fov=fov)
+    end = v - 1 if side > 0 else 0
+    inside = (measured < 0) if side > 0 else (measured >= 0)
+    strict, loose = r.dmin_strict[0], r.dmin_loose[0]
+    assert r.n_nb[0] == 1 and np.count_nonzero(np.isfinite(loose)) == (1 if (ambiguous or inside) else 0)
+    if ambiguous:
+        assert np.isinf(strict).all() and np.isfinite(loose[end])
+    elif inside:
+        assert np.isfinite(strict[end]) and np.array_equal(strict, loose)
+    else:
+        assert np.isinf(strict).all() and np.isinf(loose).all()
+
+
+@pytest.mark.parametrize("offset,ambiguous", [(0.85e-5, True), (-0.85e-5, True), (2e-5, False)])
+def test_band_width_tag(oracle_mod, offset, ambiguous):
+    """The tag oracle's bands have the flock's widths: a runner pair (channel
+    0) at a 250-degree sector edge and a runner-chaser pair at the touch distance."""
+    heading, v, fov = 0.4, 64, math.radians(250.0)
+    rel_edge = -fov / 2 + 20 * fov / v
+    x, y, th, _, bearing = _pair_at(7.5, heading + rel_edge + offset, heading=heading)
+    measured = math.remainder(bearing - float(np.float32(heading)) - rel_edge, 2 * math.pi)
+    assert abs(measured - offset) < 5e-7
+    r = oracle_mod.oracle_sense_tag(x, y, th, 64.0, 0, radius=10.0, touch=1.0, sectors=v,
+                                    agents=[0], eps_d=EPS, eps_phi=EPS, fov=fov)
+    assert np.count_nonzero(np.isfinite(r.dmin_loose[0])) == (2 if ambiguous else 1)
+    assert np.count_nonzero(np.isfinite(r.dmin_strict[0])) == (0 if ambiguous else 1)
+    x, y, th, d, _ = _pair_at(1.0 + offset, 1.1)
+    assert abs((d - 1.0) - offset) < 2e-6
+    r = oracle_mod.oracle_sense_tag(x, y, th, 64.0, 1, radius=10.0, touch=1.0, sectors=v,
+                                    agents=[0, 1], eps_d=EPS, eps_phi=EPS, fov=fov)
+    touch = int(d < 1.0)
+    for k in range(2):
+        assert (r.col_lo[k], r.col_hi[k]) == ((0, 1) if ambiguous else (touch, touch))

@@ -13,8 +13,14 @@ Tolerances (stated once, applied everywhere):
     distances.  The GPU obs error from FP32 d^2 and sqrt is about 1e-7.
   * reward: |r_gpu - r| <= 1e-5 * max(1, |r|), r computed in FP64 from the
     counts.
-  * state after the move: bitwise equal (both sides compute the same FP32
-    operations with correctly rounded cos/sin).
+  * state after the move, teacher-forced (the oracle moves the GPU's own
+    pre-step state with the same actions): heading and speed bitwise equal
+    (the same FP32 operations on both sides); each coordinate within
+    MOVE_POS_TOL = 2^-21 plus one ulp of the oracle's value, periodically.
+    The GPU's FP32 cos/sin are within 1 ulp of the correctly rounded values
+    the oracle uses; scaled by a speed of at most 2 that moves the step
+    s cos(theta) by at most 2^-22 before its rounding, and the sum x + step
+    by at most one rounding more.
 """
 from __future__ import annotations
 
@@ -24,6 +30,7 @@ EPS_D = 1e-5
 EPS_PHI = 1e-5
 OBS_TOL = 1e-5
 REW_TOL = 1e-5
+MOVE_POS_TOL = 2.0 ** -21
 
 
 def check_sense(oracle_res, obs, reward, nb, col, radius=8.0, r_nb=0.1, r_col=-1.0, label=""):
@@ -77,3 +84,26 @@ def state_mismatch(a, b):
         idx |= d != 0
         ulp = max(ulp, int(np.abs(d).max(initial=0)))
     return np.nonzero(idx)[0], ulp
+
+
+def check_move(got, want, box, label=""):
+    """GPU post-move state ``got`` against the oracle's move ``want`` of the same
+    pre-move state (tuples x, y, heading, speed); returns the largest position
+    error in units of the tolerance."""
+    gx, gy, gth, gs = (np.asarray(a, np.float32) for a in got)
+    wx, wy, wth, ws = (np.asarray(a, np.float32) for a in want)
+    bad = np.nonzero((gth.view(np.int32) != wth.view(np.int32)) |
+                     (gs.view(np.int32) != ws.view(np.int32)))[0]
+    assert bad.size == 0, f"{label}: heading/speed differ at {bad[:10]}"
+    worst = 0.0
+    for g, w, name in ((gx, wx, "x"), (gy, wy, "y")):
+        d = g.astype(np.float64) - w.astype(np.float64)
+        d -= box * np.round(d / box)          # a wrap decided on either side of 0 or L
+        tol = MOVE_POS_TOL + np.spacing(np.abs(w)).astype(np.float64)
+        r = np.abs(d) / tol
+        if r.size:
+            worst = max(worst, float(r.max()))
+        assert (r <= 1.0).all(), (f"{label}: {name} off by {d[r > 1][:5]} at "
+                                  f"{np.nonzero(r > 1)[0][:5]} (tolerance {tol[r > 1][:5]})")
+        assert ((g >= 0) & (g < box)).all(), f"{label}: {name} outside [0, L)"
+    return worst

@@ -2,9 +2,10 @@
 
 v = 128 sectors over a 250-degree field of view, the agent's speed appended
 to its view (129 values per row), vision range one tenth of the box side.
-The oracle gets the same FP32 state and actions; the GPU view must lie in
-the oracle's bands, the speed column must equal the post-move speed
-bitwise, and the post-move state must match bitwise.
+Checks are teacher-forced: the oracle moves the GPU's pre-step state with the
+same actions (heading and speed bitwise, positions within the move
+tolerance) and senses the GPU's post-move state; the view must lie in the
+oracle's bands and the speed column must equal the post-move speed bitwise.
 """
 from __future__ import annotations
 
@@ -16,7 +17,7 @@ import torch
 
 import oracle
 import workloads
-from parity import EPS_D, EPS_PHI, check_sense, state_mismatch
+from parity import EPS_D, EPS_PHI, check_move, check_sense
 
 pytestmark = pytest.mark.gpu
 flock = pytest.importorskip("paper_2207_03945_amd")
@@ -47,11 +48,18 @@ def oracle_band(st, p, agents=None):
                                eps_d=EPS_D, eps_phi=EPS_PHI, fov=fov)
 
 
-def check_rows(env, st, p, obs, rew, agents=None, label=""):
+def gpu_state(env):
+    return tuple(host(t) for t in env.get_state())
+
+
+def check_rows(env, pre, act, p, obs, rew, agents=None, label=""):
+    """Rows after a step with actions ``act`` from GPU state ``pre`` (act None:
+    after the reset of state ``pre``), teacher-forced."""
     torch.cuda.synchronize()
-    got = tuple(host(t) for t in env.get_state())
-    bad, ulp = state_mismatch(got, st)
-    assert bad.size == 0, f"{label}: state differs at {bad[:10]} (max {ulp} ulp)"
+    st = gpu_state(env)
+    want = pre if act is None else oracle.oracle_move(pre, act, p.box, p.max_turn, p.max_dspeed,
+                                                      p.s_min, p.s_max)
+    check_move(st, want, p.box, label)
     rows = slice(None) if agents is None else agents
     o = host(obs)[rows]
     v = p.sectors
@@ -63,26 +71,30 @@ def check_rows(env, st, p, obs, rew, agents=None, label=""):
                        radius=p.radius, r_nb=p.r_nb, r_col=p.r_col, label=label)
 
 
-def run_case(p, st, steps, check_at, n_sample=None, seed=0, label=""):
+def run_case(p, st, steps, check_at, n_sample=None, seed=0, label="", lanes=0):
     env = flock.Env(p)
     env.set_state(*[dev(a) for a in st])
     obs0 = env.reset()
+    if lanes:
+        env.set_sweep_lanes(lanes)
     g = np.random.default_rng(seed + 7)
     n = p.n_agents
-    stats = [check_rows(env, st, p, obs0, 0.1 * host(env.counts()[0]) - host(env.counts()[1]),
+    stats = [check_rows(env, st, None, p, obs0, 0.1 * host(env.counts()[0]) - host(env.counts()[1]),
                         label=f"{label} reset")] if n_sample is None else []
     obs = torch.empty(n, p.obs_dim, device="cuda")
     rew = torch.empty(n, device="cuda")
     for t in range(steps):
         act = workloads.random_actions(n, seed=seed, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, p.box, p.max_turn, p.max_dspeed, p.s_min, p.s_max)
         if t in check_at:
+            pre = gpu_state(env)
+            env.step(dev(act), obs, rew)
             agents = None
             if n_sample is not None:
                 agents = np.sort(g.choice(n, size=min(n_sample, n), replace=False)).astype(np.int32)
-            stats.append(check_rows(env, st, p, obs, rew, agents, label=f"{label} step {t}"))
-    return env, st, stats
+            stats.append(check_rows(env, pre, act, p, obs, rew, agents, label=f"{label} step {t}"))
+        else:
+            env.step(dev(act), obs, rew)
+    return env, stats
 
 
 def test_paper_flock1k_every_agent():
@@ -90,7 +102,7 @@ def test_paper_flock1k_every_agent():
     cfg = workloads.WORKLOADS["paper_flock1k"]
     p = params_for(cfg)
     st = workloads.make_state(cfg, seed=0)
-    _, _, stats = run_case(p, st, 20, set(range(20)), label="paper_flock1k")
+    _, stats = run_case(p, st, 20, set(range(20)), label="paper_flock1k")
     print("ambiguous sector cells per step:", [s["ambiguous_sector_cells"] for s in stats])
 
 
@@ -100,6 +112,40 @@ def test_paper_flock10k_sampled():
     p = params_for(cfg)
     st = workloads.make_state(cfg, seed=1)
     run_case(p, st, cfg["steps"], {0, 1, 2, 50, 127}, n_sample=1500, seed=1, label="paper_flock10k")
+
+
+@pytest.mark.parametrize("reach,lanes", [(2, 16), (2, 4), (1, 16)])
+def test_paper_flock10k_batch_at_timed_settings(reach, lanes):
+    """Three 10,000-agent envs batched as the paper-scale leg is timed: cell reach
+    2 and 16 lanes per agent (the tuner's choice), and the neighbouring settings;
+    500 sampled rows of each env checked at three of six steps."""
+    cfg = workloads.WORKLOADS["paper_flock10k"]
+    p = params_for(cfg, cell_reach=reach)
+    envs, sts = [], []
+    for k in range(3):
+        st = workloads.make_state(cfg, seed=40 + k)
+        e = flock.Env(p)
+        e.set_state(*[dev(a) for a in st])
+        e.reset()
+        envs.append(e)
+        sts.append(st)
+    assert envs[0].geometry()[2] == reach
+    b = flock.Batch(envs)
+    b.set_sweep_lanes(lanes)
+    G, off, n = b.n, b.offsets, p.n_agents
+    obs = torch.empty(G, p.obs_dim, device="cuda")
+    rew = torch.empty(G, device="cuda")
+    g = np.random.default_rng(reach * 100 + lanes)
+    for t in range(6):
+        act = workloads.random_actions(G, seed=41, step=t)
+        pre = [gpu_state(e) for e in envs]
+        b.step(dev(act), obs, rew)
+        if t in (0, 2, 5):
+            for k in range(3):
+                agents = np.sort(g.choice(n, 500, replace=False)).astype(np.int32)
+                rows = slice(off[k], off[k + 1])
+                check_rows(envs[k], pre[k], act[off[k]:off[k + 1]], p, obs[rows], rew[rows], agents,
+                           label=f"env {k} step {t} reach {reach} lanes {lanes}")
 
 
 @pytest.mark.parametrize("v", [1, 2, 7, 16, 129])
@@ -138,7 +184,7 @@ def test_coincident_agents_seen_straight_ahead():
         assert obs[i, v // 2] == 1.0 and np.count_nonzero(obs[i]) == 1, obs[i]
     assert not obs[2].any()
     nb, col = env.counts()
-    check_rows(env, (x, y, th, s), p, torch.from_numpy(obs), 0.1 * nb.float() - col.float(),
+    check_rows(env, (x, y, th, s), None, p, torch.from_numpy(obs), 0.1 * nb.float() - col.float(),
                label="coincident")
 
 

@@ -1,9 +1,10 @@
 """GPU parity: the HIP step against the CPU oracle, through the C ABI.
 
-Every case draws seeded synthetic inputs from ``workloads``; the oracle sees
-the same FP32 state and actions as the GPU.  The post-move state must match
-bitwise; counts, view and reward must match within the bands of
-``tests/parity.py``.
+Every case draws seeded synthetic inputs from ``workloads``.  Checks are
+teacher-forced: the oracle moves the GPU's own pre-step state with the same
+actions (heading and speed must match bitwise, positions within the move
+tolerance of ``tests/parity.py``), and senses the GPU's post-move state
+(counts, view and reward within the bands of ``tests/parity.py``).
 """
 from __future__ import annotations
 
@@ -15,7 +16,7 @@ import torch
 
 import oracle
 import workloads
-from parity import EPS_D, EPS_PHI, REW_TOL, check_sense, state_mismatch
+from parity import EPS_D, EPS_PHI, REW_TOL, check_move, check_sense
 
 pytestmark = pytest.mark.gpu
 
@@ -47,15 +48,22 @@ def gpu_state(env):
     return tuple(host(t) for t in env.get_state())
 
 
-def check_step(env, st_oracle, box, v, obs, rew, agents=None, label=""):
+def check_post(env, pre, act, box, v, obs, rew, agents=None, label=""):
+    """Teacher-forced check of the step just taken from GPU state ``pre``."""
     torch.cuda.synchronize()
-    st_gpu = gpu_state(env)
-    bad, ulp = state_mismatch(st_gpu, st_oracle)
-    assert bad.size == 0, f"{label}: state differs at {bad[:10]} (max {ulp} ulp)"
+    post = gpu_state(env)
+    check_move(post, oracle.oracle_move(pre, act, box), box, label)
     nb, col = (host(t) for t in env.counts())
-    o = band(st_oracle, box, v, agents)
+    o = band(post, box, v, agents)
     rows = slice(None) if agents is None else agents
     return check_sense(o, host(obs)[rows], host(rew)[rows], nb[rows], col[rows], label=label)
+
+
+def step_checked(env, act, obs, rew, box, v, agents=None, label=""):
+    """One env step with actions ``act`` (host), checked teacher-forced."""
+    pre = gpu_state(env)
+    env.step(dev(act), obs, rew)
+    return check_post(env, pre, act, box, v, obs, rew, agents, label)
 
 
 # --------------------------------------------------------------------------- reset
@@ -75,21 +83,26 @@ def test_reset_view(name):
 
 # --------------------------------------------------------------------------- full runs
 
-def test_flock256_all_steps():
-    """256 agents, 64 x 64, 8 sectors, 100 steps: every step, every agent."""
+LANES = pytest.mark.parametrize("lanes", [0, 1], ids=["auto-lanes", "one-lane"])
+
+
+@LANES
+def test_flock256_all_steps(lanes):
+    """256 agents, 64 x 64, 8 sectors, 100 steps: every step, every agent; the
+    automatic sweep lanes (64 per agent for so few agents) and one lane."""
     cfg = workloads.WORKLOADS["flock256"]
     box, v, n = cfg["box"], cfg["sectors"], cfg["n"]
     st = workloads.make_state("flock256", seed=0)
     env, _ = make_env(st, box, v)
+    if lanes:
+        env.set_sweep_lanes(lanes)
     obs = torch.empty(n, v, device="cuda")
     rew = torch.empty(n, device="cuda")
     ret_oracle = np.zeros(n)
     for t in range(cfg["steps"]):
         act = workloads.random_actions(n, seed=0, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, box)
-        check_step(env, st, box, v, obs, rew, label=f"flock256 step {t}")
-        ret_oracle += band(st, box, v).reward
+        step_checked(env, act, obs, rew, box, v, label=f"flock256 step {t}")
+        ret_oracle += band(gpu_state(env), box, v).reward
     ret = host(env.returns())
     np.testing.assert_allclose(ret, ret_oracle, rtol=1e-5, atol=1e-5)
 
@@ -106,11 +119,12 @@ def _run_sampled(name, check_at, n_sample, seed=0):
     stats = []
     for t in range(last + 1):
         act = workloads.random_actions(n, seed=seed, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, box)
         if t in check_at:
             agents = np.sort(g.choice(n, size=min(n_sample, n), replace=False)).astype(np.int32)
-            stats.append(check_step(env, st, box, v, obs, rew, agents=agents, label=f"{name} step {t}"))
+            stats.append(step_checked(env, act, obs, rew, box, v, agents=agents,
+                                      label=f"{name} step {t}"))
+        else:
+            env.step(dev(act), obs, rew)
     return stats
 
 
@@ -131,22 +145,29 @@ def test_uniform50k_sampled_steps():
 def test_flock5k_x200_graph_replay_sampled():
     """The 200 x 5,000-agent batch (side 316, 16 sectors) as it is timed: K steps
     captured in one graph, replayed twice with new actions written between the
-    replays (one-block-per-env sort, one lane per agent).  Every env's state
-    after both replays bitwise; every step's reward of 300 sampled agents in six
-    envs (both ends of the batch, block-index seams) against the oracle; the
-    last step's view and counts of those agents."""
+    replays.  A twin batch of the same envs steps the same actions eagerly, each
+    step checked teacher-forced against the oracle on 300 sampled agents in six
+    envs (both ends of the batch, block-index seams); the replayed rewards of
+    every step, the last view, every env's state and returns equal the twin's
+    bitwise."""
     n, box, v, E, K = 5000, 316.0, 16, 200, 4
     sts = [workloads.uniform_state(n, box, seed=500 + k) for k in range(E)]
     envs = [make_env(st, box, v)[0] for st in sts]
-    batch = flock.Batch(envs)
+    twins = [make_env(st, box, v)[0] for st in sts]
+    batch, eager = flock.Batch(envs), flock.Batch(twins)
     G, off = batch.n, batch.offsets
     assert G == n * E
     obs = torch.empty(G, v, device="cuda")
     rew = torch.empty(K, G, device="cuda")
     act = torch.empty(K, G, 2, device="cuda")
+    obs_e = torch.empty(G, v, device="cuda")
+    rew_e = torch.empty(G, device="cuda")
     stream = torch.cuda.Stream()
     acts = [[workloads.random_actions(n, seed=5, step=t, env=k) for k in range(E)]
             for t in range(2 * K)]
+    sample = [0, 1, 63, 64, 128, 199]
+    g = np.random.default_rng(8)
+    agents = {k: np.sort(g.choice(n, 300, replace=False)).astype(np.int32) for k in sample}
     for rep in range(2):
         act.copy_(dev(np.stack([np.concatenate(acts[rep * K + t]) for t in range(K)])))
         torch.cuda.synchronize()
@@ -155,35 +176,27 @@ def test_flock5k_x200_graph_replay_sampled():
                 batch.capture(K, act, obs, rew, stream)
             batch.run(K, act, obs, rew, stream)
         stream.synchronize()
-    rew_h, obs_h = host(rew), host(obs)
-    sample = {0, 1, 63, 64, 128, 199}
-    g = np.random.default_rng(8)
+        for t in range(K):
+            pre = {k: gpu_state(twins[k]) for k in sample}
+            eager.step(act[t], obs_e, rew_e)
+            for k in sample:
+                rows = slice(off[k], off[k + 1])
+                check_post(twins[k], pre[k], acts[rep * K + t][k], box, v, obs_e[rows],
+                           rew_e[rows], agents[k], label=f"env {k} replay {rep} step {t}")
+            assert torch.equal(rew[t], rew_e), f"replay {rep} step {t}: rewards differ"
+        assert torch.equal(obs, obs_e), f"replay {rep}: view differs"
     for k in range(E):
-        st = sts[k]
-        agents = np.sort(g.choice(n, 300, replace=False)).astype(np.int32) if k in sample else None
-        for t in range(2 * K):
-            st = oracle.oracle_move(st, acts[t][k], box)
-            if agents is not None and t >= K:
-                rows = off[k] + agents
-                if t < 2 * K - 1:  # the view buffer holds the last step only: rewards here
-                    o = band(st, box, v, agents)
-                    amb = (o.nb_lo != o.nb_hi) | (o.col_lo != o.col_hi)
-                    r = rew_h[t - K][rows].astype(np.float64)
-                    rerr = np.abs(r - o.reward) / np.maximum(1.0, np.abs(o.reward))
-                    assert rerr[~amb].max(initial=0.0) <= REW_TOL, f"env {k} step {t}: {rerr.max()}"
-                else:
-                    nb, col = (host(x) for x in envs[k].counts())
-                    check_sense(band(st, box, v, agents), obs_h[rows], rew_h[t - K][rows],
-                                nb[agents], col[agents], label=f"env {k} last step")
-        bad, ulp = state_mismatch(gpu_state(envs[k]), st)
-        assert bad.size == 0, f"env {k}: state differs at {bad[:10]} (max {ulp} ulp)"
+        assert all(torch.equal(a, b) for a, b in zip(envs[k].get_state(), twins[k].get_state()))
+        assert torch.equal(envs[k].returns(), twins[k].returns())
 
 
 # --------------------------------------------------------------------------- edge cases
 
-def _one_step_case(st, box, v, reach=0, steps=3, seed=0):
+def _one_step_case(st, box, v, reach=0, steps=3, seed=0, lanes=0):
     n = st[0].shape[0]
     env, obs0 = make_env(st, box, v, reach=reach)
+    if lanes:
+        env.set_sweep_lanes(lanes)
     torch.cuda.synchronize()
     if n > 0:
         nb, col = (host(t) for t in env.counts())
@@ -192,10 +205,10 @@ def _one_step_case(st, box, v, reach=0, steps=3, seed=0):
     rew = torch.empty(n, device="cuda")
     for t in range(steps):
         act = workloads.random_actions(n, seed=seed, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, box)
         if n > 0:
-            check_step(env, st, box, v, obs, rew, label=f"step {t}")
+            step_checked(env, act, obs, rew, box, v, label=f"step {t}")
+        else:
+            env.step(dev(act), obs, rew)
     torch.cuda.synchronize()
     return env
 
@@ -205,35 +218,40 @@ def test_empty_env():
     _one_step_case(st, 64.0, 8)
 
 
+@LANES
 @pytest.mark.parametrize("n", [1, 2, 3])
-def test_tiny_envs(n):
+def test_tiny_envs(n, lanes):
     st = workloads.uniform_state(n, 20.0, seed=n)
-    _one_step_case(st, 20.0, 8)
+    _one_step_case(st, 20.0, 8, lanes=lanes)
 
 
+@LANES
 @pytest.mark.parametrize("box", [16.5, 20.0, 24.0, 24.5, 33.0])
-def test_small_boxes_all_pairs_and_three_cells(box):
+def test_small_boxes_all_pairs_and_three_cells(box, lanes):
     n = int(box * box / 4)
     st = workloads.uniform_state(n, box, seed=3)
-    env = _one_step_case(st, box, 16)
+    env = _one_step_case(st, box, 16, lanes=lanes)
     ncell, _, reach, _, _ = env.geometry()
     assert (ncell == 1) == (box <= 24.0)
     assert ncell == 1 or ncell >= 3
 
 
+@LANES
 @pytest.mark.parametrize("v", [1, 3, 8, 16, 33, 64, 128, 256])
-def test_sector_counts(v):
+def test_sector_counts(v, lanes):
     st = workloads.uniform_state(2000, 120.0, seed=v)
-    _one_step_case(st, 120.0, v, steps=2)
+    _one_step_case(st, 120.0, v, steps=2, lanes=lanes)
 
 
-def test_reach_two_stencil():
+@LANES
+def test_reach_two_stencil(lanes):
     st = workloads.uniform_state(4000, 160.0, seed=4)
-    env = _one_step_case(st, 160.0, 16, reach=2)
+    env = _one_step_case(st, 160.0, 16, reach=2, lanes=lanes)
     assert env.geometry()[2] == 2
 
 
-def test_dense_cluster_and_coincident():
+@LANES
+def test_dense_cluster_and_coincident(lanes):
     """Skewed occupancy: most agents inside one cell, many exact duplicates."""
     g = np.random.default_rng(5)
     n, box = 3000, 200.0
@@ -243,10 +261,11 @@ def test_dense_cluster_and_coincident():
     y[::7] = y[0]
     th = (g.random(n) * 6.28).astype(np.float32)
     s = np.zeros(n, np.float32)
-    _one_step_case((x, y, th, s), box, 16, steps=2)
+    _one_step_case((x, y, th, s), box, 16, steps=2, lanes=lanes)
 
 
-def test_cell_boundaries_and_seams():
+@LANES
+def test_cell_boundaries_and_seams(lanes):
     """Agents exactly on column and row boundaries, at 0 and just below the box side."""
     box, v = 64.0, 16
     env0 = flock.Env(flock.Params(n_agents=10000, box=box, sectors=v))
@@ -259,7 +278,7 @@ def test_cell_boundaries_and_seams():
     n = x.shape[0]
     th = (np.arange(n) * 0.37 % 6.2).astype(np.float32)
     s = np.zeros(n, np.float32)
-    _one_step_case((x, y, th, s), box, v, steps=2)
+    _one_step_case((x, y, th, s), box, v, steps=2, lanes=lanes)
 
 
 def test_single_large_env():
@@ -269,12 +288,10 @@ def test_single_large_env():
     env, _ = make_env(st, box, v)
     obs = torch.empty(n, v, device="cuda")
     rew = torch.empty(n, device="cuda")
+    agents = np.sort(np.random.default_rng(1).choice(n, 2000, replace=False)).astype(np.int32)
     for t in range(2):
         act = workloads.random_actions(n, seed=8, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, box)
-    agents = np.sort(np.random.default_rng(1).choice(n, 2000, replace=False)).astype(np.int32)
-    check_step(env, st, box, v, obs, rew, agents=agents, label="1M env")
+        step_checked(env, act, obs, rew, box, v, agents=agents, label=f"1M env step {t}")
 
 
 def test_sparse_env_many_cells():
@@ -287,12 +304,10 @@ def test_sparse_env_many_cells():
     assert ncx * ncy > 4096 * 2048
     obs = torch.empty(n, v, device="cuda")
     rew = torch.empty(n, device="cuda")
+    agents = np.sort(np.random.default_rng(2).choice(n, 2000, replace=False)).astype(np.int32)
     for t in range(2):
         act = workloads.random_actions(n, seed=9, step=t)
-        env.step(dev(act), obs, rew)
-        st = oracle.oracle_move(st, act, box)
-    agents = np.sort(np.random.default_rng(2).choice(n, 2000, replace=False)).astype(np.int32)
-    check_step(env, st, box, v, obs, rew, agents=agents, label="16.7M-cell env")
+        step_checked(env, act, obs, rew, box, v, agents=agents, label=f"16.7M-cell env step {t}")
 
 
 # --------------------------------------------------------------------------- batched
@@ -320,6 +335,7 @@ def test_batched_equals_plain_bitwise():
         envs_a.append(make_env(st, b, 16, reach=r)[0])
         envs_b.append(make_env(st, b, 16, reach=r)[0])
     batch = flock.Batch(envs_b)
+    batch.set_sweep_lanes(1)   # one lane per agent against each env's automatic lane groups
     G = batch.n
     obs_b = torch.empty(G, 16, device="cuda")
     rew_b = torch.empty(G, device="cuda")
@@ -364,24 +380,22 @@ def test_sweep_lane_groups_bitwise_equal_to_one_lane(lanes):
     G, off = batch.n, batch.offsets
     obs_b = torch.empty(G, 16, device="cuda")
     rew_b = torch.empty(G, device="cuda")
+    agents = np.sort(np.random.default_rng(lanes).choice(50000, 1500, replace=False)).astype(np.int32)
     for t in range(3):
         acts = [workloads.random_actions(st[0].shape[0], seed=2, step=t, env=k)
                 for k, st in enumerate(states)]
+        pre = gpu_state(grp[0])
         batch.step(dev(np.concatenate(acts).reshape(G, 2)), obs_b, rew_b)
         for k, env in enumerate(ref):
             o, r = env.step(dev(acts[k]))
             assert torch.equal(o, obs_b[off[k]:off[k + 1]]), f"obs env {k} step {t}"
             assert torch.equal(r, rew_b[off[k]:off[k + 1]]), f"reward env {k} step {t}"
+        if t == 2:   # and against the oracle on sampled agents of the clustered env
+            check_post(grp[0], pre, acts[0], 1000.0, 16, obs_b[off[0]:off[1]],
+                       rew_b[off[0]:off[1]], agents=agents, label=f"lanes {lanes}")
     for ea, eb in zip(ref, grp):
         assert torch.equal(ea.returns(), eb.returns())
         assert all(torch.equal(u, w) for u, w in zip(ea.counts(), eb.counts()))
-    # and against the oracle on sampled agents of the clustered env
-    st = states[0]
-    for t in range(3):
-        st = oracle.oracle_move(st, workloads.random_actions(50000, seed=2, step=t, env=0), 1000.0)
-    agents = np.sort(np.random.default_rng(lanes).choice(50000, 1500, replace=False)).astype(np.int32)
-    check_step(grp[0], st, 1000.0, 16, obs_b[off[0]:off[1]], rew_b[off[0]:off[1]], agents=agents,
-               label=f"lanes {lanes}")
 
 
 @pytest.mark.parametrize("big", [0, 5000, 12000])
@@ -407,34 +421,31 @@ def test_per_env_fused_sort_batch_bitwise_and_oracle(big):
     G, off = batch.n, batch.offsets
     obs_b = torch.empty(G, 16, device="cuda")
     rew_b = torch.empty(G, device="cuda")
-    acts_all = []
+    g = np.random.default_rng(4)
+    check = [k for k in sorted(set(range(0, len(sts), 10)) | {len(sts) - 1}) if sts[k][0].shape[0]]
+    agents = {k: np.sort(g.choice(sts[k][0].shape[0], size=min(20, sts[k][0].shape[0]),
+                                  replace=False)).astype(np.int32) for k in check}
     for t in range(6):
         acts = [workloads.random_actions(st[0].shape[0], seed=3, step=t, env=k)
                 for k, st in enumerate(sts)]
-        acts_all.append(acts)
+        pre = {k: gpu_state(fused[k]) for k in check} if t == 5 else {}
         batch.step(dev(np.concatenate(acts).reshape(G, 2)), obs_b, rew_b)
         for k, env in enumerate(plain):
             o, r = env.step(dev(acts[k]))
             assert torch.equal(o, obs_b[off[k]:off[k + 1]]), f"obs env {k} step {t}"
             assert torch.equal(r, rew_b[off[k]:off[k + 1]]), f"reward env {k} step {t}"
+        for k in pre:   # the last step against the oracle on sampled agents
+            check_post(fused[k], pre[k], acts[k], bxs[k], 16, obs_b[off[k]:off[k + 1]],
+                       rew_b[off[k]:off[k + 1]], agents=agents[k], label=f"fused env {k}")
     for ea, eb in zip(plain, fused):
         assert torch.equal(ea.returns(), eb.returns())
         assert all(torch.equal(u, w) for u, w in zip(ea.get_state(), eb.get_state()))
-    g = np.random.default_rng(4)
-    for k in sorted(set(range(0, len(sts), 10)) | {len(sts) - 1}):
-        st = sts[k]
-        for t in range(6):
-            st = oracle.oracle_move(st, acts_all[t][k], bxs[k])
-        n = st[0].shape[0]
-        if n == 0:
-            continue
-        agents = np.sort(g.choice(n, size=min(20, n), replace=False)).astype(np.int32)
-        check_step(fused[k], st, bxs[k], 16, obs_b[off[k]:off[k + 1]], rew_b[off[k]:off[k + 1]],
-                   agents=agents, label=f"fused env {k}")
 
 
 def test_batched_uneven_256_envs_against_oracle():
-    """256 envs, N_e log-uniform in [100, 20,000] at density 1/16: sampled agents per env."""
+    """256 envs, N_e log-uniform in [100, 20,000] at density 1/16, 200 steps: 16
+    sampled agents of every env checked teacher-forced at steps 0, 1, 2, 10 and
+    199 (device-drawn actions in between)."""
     ns, boxes, states = _uneven(256, 100, 20000, seed=0)
     envs = [make_env(st, float(b), 16)[0] for st, b in zip(states, boxes)]
     batch = flock.Batch(envs)
@@ -442,20 +453,24 @@ def test_batched_uneven_256_envs_against_oracle():
     off = batch.offsets
     obs = torch.empty(G, 16, device="cuda")
     rew = torch.empty(G, device="cuda")
-    acts = [workloads.random_actions(int(n), seed=0, step=0, env=k) for k, n in enumerate(ns)]
-    batch.step(dev(np.concatenate(acts)), obs, rew)
-    torch.cuda.synchronize()
-    obs_h, rew_h = host(obs), host(rew)
     g = np.random.default_rng(3)
-    for k in range(256):
-        st = oracle.oracle_move(states[k], acts[k], float(boxes[k]))
-        bad, _ = state_mismatch(gpu_state(envs[k]), st)
-        assert bad.size == 0, f"env {k}"
-        agents = np.sort(g.choice(int(ns[k]), size=min(8, int(ns[k])), replace=False)).astype(np.int32)
-        nb, col = (host(t) for t in envs[k].counts())
-        o = band(st, float(boxes[k]), 16, agents)
-        rows = off[k] + agents
-        check_sense(o, obs_h[rows], rew_h[rows], nb[agents], col[agents], label=f"env {k}")
+    agents = [np.sort(g.choice(int(n), size=min(16, int(n)), replace=False)).astype(np.int32)
+              for n in ns]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    scale = torch.tensor([0.2, 0.1], device="cuda")
+    for t in range(200):
+        if t not in (0, 1, 2, 10, 199):
+            act = (torch.rand(G, 2, device="cuda", generator=gen) * 2.0 - 1.0) * scale
+            batch.step(act, obs, rew)
+            continue
+        acts = [workloads.random_actions(int(n), seed=0, step=t, env=k) for k, n in enumerate(ns)]
+        pre = [gpu_state(e) for e in envs]
+        batch.step(dev(np.concatenate(acts)), obs, rew)
+        for k in range(256):
+            rows = slice(off[k], off[k + 1])
+            check_post(envs[k], pre[k], acts[k], float(boxes[k]), 16, obs[rows], rew[rows],
+                       agents=agents[k], label=f"env {k} step {t}")
 
 
 @pytest.mark.parametrize("n_envs", [10, 80])   # 80: the one-block-per-env sort
@@ -522,3 +537,39 @@ def test_timed_step_equals_step(n_envs):
             assert ms[1] == 0.0 and ms[2] == 0.0
         else:
             assert ms[1] > 0.0 and ms[2] > 0.0
+
+
+# --------------------------------------------------------------------------- move arithmetic
+
+def test_move_cos_sin_within_one_ulp():
+    """The move's FP32 cos/sin against the correctly rounded values the oracle uses.
+
+    An agent at x = 0 with speed 1 and no action lands at x' = cos h whenever
+    cos h >= 0 (x + 1 * cos h is then exact), so its new x exposes the
+    kernel's cosine; likewise y = 0 exposes the sine.  131,072 headings spread
+    over the first quadrant (the others use the same polynomials with swapped
+    roles and signs) plus its edges, in two envs: x = 0 with the agents spread
+    over 128 rows 0.5 apart (vision 0.4, so a row's agents see only each
+    other), and y = 0 with them spread over columns.  Every exposed value
+    within 1 ulp of the oracle's, and nearly all equal.
+    """
+    g = np.random.default_rng(17)
+    h = np.concatenate([g.random(131_068) * (np.pi / 2), [0.0, np.pi / 4, np.pi / 2,
+                        float(np.nextafter(np.float32(np.pi / 2), np.float32(0)))]])
+    h = h.astype(np.float32)
+    h = h[(np.cos(h.astype(np.float64)) >= 0) & (np.sin(h.astype(np.float64)) >= 0)]
+    n = h.shape[0]
+    lane = (0.5 * (np.arange(n) % 128)).astype(np.float32)
+    zero = np.zeros(n, np.float32)
+    act = np.zeros((n, 2), np.float32)
+    for k, name, st in ((0, "cos", (zero, lane, h, np.ones(n, np.float32))),
+                        (1, "sin", (lane, zero.copy(), h, np.ones(n, np.float32)))):
+        env = flock.Env(flock.Params(n_agents=n, box=128.0, radius=0.4, collide=0.4, sectors=8))
+        env.set_state(*[dev(a) for a in st])
+        env.reset()
+        env.step(dev(act))
+        got = gpu_state(env)[k].view(np.int32).astype(np.int64)
+        want = oracle.oracle_move(st, act, 128.0)[k].view(np.int32).astype(np.int64)
+        ulp = np.abs(got - want)
+        assert ulp.max() <= 1, f"{name}: {ulp.max()} ulp at heading {h[np.argmax(ulp)]!r}"
+        assert (ulp == 0).mean() > 0.98, f"{name}: only {(ulp == 0).mean():.4f} correctly rounded"

@@ -3,9 +3,10 @@
 * critic and sampled actions against the FP64 oracle (``oracle.rl``), within
   the first-order BF16 error bound used for the actor;
 * env_rollout against the same steps taken one call at a time (bitwise), and
-  teacher-forced against the oracle at every step (the move bitwise from the
-  GPU's own actions, the view within the bands, the actions within the
-  bound);
+  teacher-forced against the oracle at every step (the oracle moves the
+  GPU's pre-step state with the GPU's own actions: heading and speed bitwise,
+  positions within the move tolerance; the view of the GPU's post-move state
+  within the bands; the actions within the bound);
 * rl_gae bitwise against the oracle: both evaluate the same FP64 operations
   in the same order on the same FP32 inputs and round once.
 """
@@ -20,7 +21,7 @@ import torch
 import oracle
 import workloads
 from oracle import rl
-from parity import EPS_D, EPS_PHI, check_sense, state_mismatch
+from parity import EPS_D, EPS_PHI, check_move, check_sense
 
 pytestmark = pytest.mark.gpu
 flock = pytest.importorskip("paper_2207_03945_amd")
@@ -143,7 +144,6 @@ def test_rollout_equals_stepwise_and_oracle_teacher_forced():
     # the same steps one call at a time, checked against the oracle as they go
     obs = obs0.clone()
     rew = torch.empty(G, device="cuda")
-    sts = [tuple(a.copy() for a in st) for st in states]
     g = np.random.default_rng(9)
     for t in range(T):
         act, logp = pol.sample(obs, eps[t].contiguous(), LOG_STD)
@@ -151,6 +151,7 @@ def test_rollout_equals_stepwise_and_oracle_teacher_forced():
         ref_a, _ = rl.gaussian_sample(mean, np.array(LOG_STD, np.float64), host(eps[t]))
         bound = net_error_bound(host(obs), ws, bs, False) * np.array([0.2, 0.1]) + 1e-6
         assert (np.abs(host(act) - ref_a) <= bound).all(), f"action step {t}"
+        pre = [tuple(host(a) for a in env.get_state()) for env in envs_s]
         bs_.step(act, obs, rew)
         torch.cuda.synchronize()
         assert torch.equal(act, act_buf[t]) and torch.equal(logp, logp_buf[t]), f"step {t}"
@@ -158,19 +159,18 @@ def test_rollout_equals_stepwise_and_oracle_teacher_forced():
         act_h, obs_h, rew_h = host(act), host(obs), host(rew)
         for k, env in enumerate(envs_s):
             lo, hi = off[k], off[k + 1]
-            sts[k] = oracle.oracle_move(sts[k], act_h[lo:hi], ps[k].box)
             got = tuple(host(a) for a in env.get_state())
-            bad, _ = state_mismatch(got, sts[k])
-            assert bad.size == 0, f"state env {k} step {t}"
+            check_move(got, oracle.oracle_move(pre[k], act_h[lo:hi], ps[k].box), ps[k].box,
+                       f"state env {k} step {t}")
             agents = np.sort(g.choice(hi - lo, size=min(40, hi - lo), replace=False)).astype(np.int32)
-            o = oracle.oracle_sense(sts[k][0], sts[k][1], sts[k][2], ps[k].box, radius=ps[k].radius,
+            o = oracle.oracle_sense(got[0], got[1], got[2], ps[k].box, radius=ps[k].radius,
                                     sectors=ps[k].sectors, fov=ps[k].fov, agents=agents,
                                     eps_d=EPS_D, eps_phi=EPS_PHI)
             nb, col = (host(x) for x in env.counts())
             rows = lo + agents
             check_sense(o, obs_h[rows, :-1], rew_h[rows], nb[agents], col[agents],
                         radius=ps[k].radius, label=f"env {k} step {t}")
-            assert np.array_equal(obs_h[rows, -1], sts[k][3][agents])
+            assert np.array_equal(obs_h[rows, -1], got[3][agents])
     for e_r, e_s in zip(envs_r, envs_s):
         assert torch.equal(e_r.returns(), e_s.returns())
         assert all(torch.equal(u, w) for u, w in zip(e_r.get_state(), e_s.get_state()))

@@ -184,6 +184,13 @@ int env_get_counts(env_t *env, int32_t *n_nb, int32_t *n_col, void *stream);
 /* Per-agent undiscounted returns since env_reset (device FP64 [n]). */
 int env_get_returns(env_t *env, double *ret, void *stream);
 
+/* Overwrite the per-agent FP64 returns (device [n], agent order), for
+ * resuming an episode from a checkpoint: env_set_state, env_reset (which
+ * zeroes the returns), then env_set_returns with the saved values.  The
+ * returns are the undiscounted sums of Eq. (1)'s rewards that env_step keeps
+ * adding to.  ENV_ESTATE before env_reset. */
+int env_set_returns(env_t *env, const double *ret, void *stream);
+
 /* ---------------------------------------------------------------- batch */
 
 /* Several environments (possibly of different sizes, boxes and views;

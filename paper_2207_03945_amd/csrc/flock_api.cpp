@@ -546,6 +546,17 @@ int env_get_returns(env_t *env, double *ret, void *stream) {
     return env_returns_to(env, ret, as_stream(stream));
 }
 
+int env_set_returns(env_t *env, const double *ret, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    if (!env->reset_done) return fail(ENV_ESTATE, "env_set_returns before env_reset");
+    const int n = env->p.n_agents;
+    if (n > 0 && !ret) return fail(ENV_EINVAL, "ret is NULL");
+    hipError_t e = launch_load_returns(ret, env->lay.id[env->parity], env->lay.ret[env->parity], n,
+                                       as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "env_set_returns");
+    return ENV_OK;
+}
+
 // ------------------------------------------------------------------- batch
 
 static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *base,

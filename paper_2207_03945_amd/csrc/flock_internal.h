@@ -141,6 +141,9 @@ hipError_t launch_store_state(const float4 *rec, const int32_t *id, float *x, fl
                               float *th, float *sp, int n, hipStream_t s);
 hipError_t launch_store_returns(const double *ret, const int32_t *id, double *out, int n,
                                 hipStream_t s);
+// Agent-order returns `in` into a cell-order buffer: ret[p] = in[id[p]].
+hipError_t launch_load_returns(const double *in, const int32_t *id, double *ret, int n,
+                               hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t s);
 

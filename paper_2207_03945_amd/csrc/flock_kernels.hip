@@ -163,7 +163,9 @@ constexpr int kHistBins = 2048;
 // [-pi/4, pi/4] (minimax fits made for this kernel: relative error 3.8e-9 for
 // sin, absolute 9.6e-11 for cos) and the quadrant's swap and signs.  Checked
 // on every FP32 heading in [0, 2pi_f]: within 1 ulp of the correctly rounded
-// value, and correctly rounded for 99.4 % (cos) and 99.6 % (sin) of them.
+// value, and correctly rounded for 99.4 % (cos) and 99.6 % (sin) of them
+// (most FP32 values lie near 0); of headings drawn uniformly in value, 84 %
+// and 94 %, the final rounding of r costing up to 0.35 ulp near pi/4.
 __device__ __forceinline__ float2 heading_cs(float h) {
     const float k = __builtin_rintf(h * 0.636619772f);
     float r = __builtin_fmaf(-k, 1.57079637050628662109375f, h);
@@ -1112,6 +1114,11 @@ __global__ void k_store_returns(const double *ret, const int32_t *id, double *ou
     if (p < n) out[id[p]] = ret[p];
 }
 
+__global__ void k_load_returns(const double *in, const int32_t *id, double *ret, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) ret[p] = in[id[p]];
+}
+
 __global__ void k_zero_f64(double *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
@@ -1290,6 +1297,13 @@ hipError_t launch_store_returns(const double *ret, const int32_t *id, double *ou
                                 hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_store_returns, dim3(blocks_for(n, 256)), dim3(256), 0, s, ret, id, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_returns(const double *in, const int32_t *id, double *ret, int n,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_load_returns, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, id, ret, n);
     return hipGetLastError();
 }
 

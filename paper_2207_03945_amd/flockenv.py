@@ -101,6 +101,7 @@ def lib():
         "env_step": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_get_counts": (ctypes.c_int, [_P, _P, _P, _P]),
         "env_get_returns": (ctypes.c_int, [_P, _P, _P]),
+        "env_set_returns": (ctypes.c_int, [_P, _P, _P]),
         "env_batch_workspace_bytes": (ctypes.c_size_t, [_PP, ctypes.c_int]),
         "env_batch_create": (ctypes.c_int, [_PP, ctypes.c_int, _P, ctypes.c_size_t, _PP]),
         "env_batch_destroy": (None, [_P]),
@@ -263,6 +264,13 @@ class Env:
         ret = torch.empty(self.n, dtype=torch.float64, device=self.workspace.device)
         check(lib().env_get_returns(self.handle, _ptr(ret), _stream(stream)))
         return ret
+
+    def set_returns(self, ret, stream=None):
+        """Restore per-agent FP64 returns (after reset, when resuming an episode)."""
+        if not (isinstance(ret, torch.Tensor) and ret.is_cuda and ret.dtype == torch.float64
+                and ret.is_contiguous() and tuple(ret.shape) == (self.n,)):
+            raise TypeError(f"ret must be a contiguous float64 CUDA tensor of shape ({self.n},)")
+        check(lib().env_set_returns(self.handle, _ptr(ret), _stream(stream)))
 
 
 class Batch:

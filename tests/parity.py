@@ -20,7 +20,10 @@ Tolerances (stated once, applied everywhere):
     The GPU's FP32 cos/sin are within 1 ulp of the correctly rounded values
     the oracle uses; scaled by a speed of at most 2 that moves the step
     s cos(theta) by at most 2^-22 before its rounding, and the sum x + step
-    by at most one rounding more.
+    by at most one rounding more.  That rounding happens before the periodic
+    wrap, at the magnitude of the unwrapped sum: a coordinate that wrapped
+    from just above L to just above 0 carries an ulp of L, so within
+    WRAP_REACH of 0 the ulp of L + WRAP_REACH is allowed.
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ EPS_PHI = 1e-5
 OBS_TOL = 1e-5
 REW_TOL = 1e-5
 MOVE_POS_TOL = 2.0 ** -21
+WRAP_REACH = 4.0      # above the largest step (speed at most 2, dt = 1)
 
 
 def check_sense(oracle_res, obs, reward, nb, col, radius=8.0, r_nb=0.1, r_col=-1.0, label=""):
@@ -99,7 +103,8 @@ def check_move(got, want, box, label=""):
     for g, w, name in ((gx, wx, "x"), (gy, wy, "y")):
         d = g.astype(np.float64) - w.astype(np.float64)
         d -= box * np.round(d / box)          # a wrap decided on either side of 0 or L
-        tol = MOVE_POS_TOL + np.spacing(np.abs(w)).astype(np.float64)
+        mag = np.where(w < WRAP_REACH, np.float32(box + WRAP_REACH), np.abs(w))
+        tol = MOVE_POS_TOL + np.spacing(mag.astype(np.float32)).astype(np.float64)
         r = np.abs(d) / tol
         if r.size:
             worst = max(worst, float(r.max()))

@@ -191,6 +191,21 @@ int env_get_returns(env_t *env, double *ret, void *stream);
  * adding to.  ENV_ESTATE before env_reset. */
 int env_set_returns(env_t *env, const double *ret, void *stream);
 
+/* For callers that cannot allocate device memory or hand the library a
+ * scratch workspace at step time: code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The same step as env_step (bitwise
+ * the same results), but its sort scratch comes from a static device array
+ * of env_static_scratch_bytes() bytes (32 MiB) per GPU, held until the
+ * process ends; the call allocates nothing.  The env still owns its state
+ * in its workspace; act, obs and reward are as for env_step.  ENV_ENOMEM
+ * (before anything is enqueued) when the step needs more scratch than the
+ * array holds: about 33 bytes per agent plus 8 per grid cell, so roughly
+ * 800,000 agents at the default grid.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (two streams, or two threads) race and
+ * must be serialised by the caller.  The env's device must be current. */
+size_t env_static_scratch_bytes(void);
+int env_step_static(env_t *env, const float *act, float *obs, float *reward, void *stream);
+
 /* ---------------------------------------------------------------- batch */
 
 /* Several environments (possibly of different sizes, boxes and views;

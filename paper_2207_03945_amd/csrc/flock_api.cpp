@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -554,6 +555,75 @@ int env_set_returns(env_t *env, const double *ret, void *stream) {
     hipError_t e = launch_load_returns(ret, env->lay.id[env->parity], env->lay.ret[env->parity], n,
                                        as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_set_returns");
+    return ENV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- static step scratch
+//
+// env_step_static takes the sort scratch of its step (cell keys, ranks, moved
+// records, candidate positions, cell counts and starts, descriptor tables)
+// from `scratch`, one array per GPU that the library runs on, held until the
+// process ends, instead of from the env's workspace.  In host code the
+// array's name stands for a host-side shadow, not a device address: kernels
+// only ever get the per-device address hipGetSymbolAddress returns.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per device).
+int static_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ENV_EINVAL, "device %d: the static scratch is tracked for devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(ENV_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return ENV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t env_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int env_step_static(env_t *env, const float *act, float *obs, float *reward, void *stream) {
+    if (!env) return fail(ENV_EINVAL, "env is NULL");
+    const size_t need = sort_scratch_bytes(env->plan.G, env->plan.C, 1);
+    if (need > kStaticScratchBytes)
+        return fail(ENV_ENOMEM,
+                    "env_step_static: a step of %lld agents over %lld cells needs %zu bytes of "
+                    "scratch; the static array holds %zu (use env_step)",
+                    (long long)env->plan.G, (long long)env->plan.C, need, kStaticScratchBytes);
+    if (!env->reset_done) return fail(ENV_ESTATE, "env_step_static before env_reset");
+    const int n = env->p.n_agents;
+    if (n > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    if (n == 0) return ENV_OK;
+    void *base = nullptr;
+    int rc = static_scratch(&base);
+    if (rc != ENV_OK) return rc;
+    StepPlan p = env->plan;
+    Carver cv{static_cast<char *>(base), 0};
+    carve_sort(cv, p.G, p.C, 1, &p.a);
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_bind_one(p, env->own[0], env->own[1], n, s);
+    if (e == hipSuccess) e = launch_step(p, env->parity, 1, act, obs, reward, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "env_step_static");
+    env->parity ^= 1;
     return ENV_OK;
 }
 

@@ -117,6 +117,10 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
 // Launchers (return hipSuccess or the first error) ------------------------
 // Zero the cell counts (used once after carving).
 hipError_t launch_clear(const StepPlan &p, hipStream_t s);
+// Write a one-env plan's descriptor tables (d0 as stored, d1 with the buffers
+// swapped) and agent offsets {0, n} into its sort scratch, and zero its counts.
+hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1, int32_t n,
+                           hipStream_t s);
 // One step with descriptor table `table` (0 or 1) of the plan.
 // do_move = 0 senses the current state without moving (episode start).
 // act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]); when NULL the

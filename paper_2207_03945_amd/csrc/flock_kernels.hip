@@ -1161,6 +1161,27 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->base = cv.take<int32_t>(E + 1);
 }
 
+// Descriptor tables and agent offsets of a one-env plan, written from the
+// kernel's by-value arguments (no copy from host memory), and the plan's cell
+// counts zeroed: what a step needs in its sort scratch before it starts.
+__global__ void k_bind_one(SortArrays a, DevEnv d0, DevEnv d1, int32_t n, int64_t C) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C) a.count[i] = 0;
+    if (i == 0) {
+        a.envs[0][0] = d0;
+        a.envs[1][0] = d1;
+        a.base[0] = 0;
+        a.base[1] = n;
+    }
+}
+
+hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1, int32_t n,
+                           hipStream_t s) {
+    const int64_t c = p.C > 0 ? p.C : 1;
+    hipLaunchKernelGGL(k_bind_one, dim3(blocks_for(c, 256)), dim3(256), 0, s, p.a, d0, d1, n, p.C);
+    return hipGetLastError();
+}
+
 hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     const int64_t n = p.C > 0 ? p.C : 1;
     hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C);

@@ -102,6 +102,8 @@ def lib():
         "env_get_counts": (ctypes.c_int, [_P, _P, _P, _P]),
         "env_get_returns": (ctypes.c_int, [_P, _P, _P]),
         "env_set_returns": (ctypes.c_int, [_P, _P, _P]),
+        "env_static_scratch_bytes": (ctypes.c_size_t, []),
+        "env_step_static": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_batch_workspace_bytes": (ctypes.c_size_t, [_PP, ctypes.c_int]),
         "env_batch_create": (ctypes.c_int, [_PP, ctypes.c_int, _P, ctypes.c_size_t, _PP]),
         "env_batch_destroy": (None, [_P]),
@@ -251,6 +253,21 @@ class Env:
         _dev_f32(obs, (self.n, self.d), "obs")
         _dev_f32(reward, (self.n,), "reward")
         check(lib().env_step(self.handle, _ptr(act), _ptr(obs), _ptr(reward), _stream(stream)))
+        return obs, reward
+
+    def step_static(self, act, obs=None, reward=None, stream=None):
+        """As :meth:`step`, with the step's scratch in the library's static
+        device array (env_step_static): nothing is allocated by the call."""
+        dev = self.workspace.device
+        if obs is None:
+            obs = torch.empty(self.n, self.d, dtype=torch.float32, device=dev)
+        if reward is None:
+            reward = torch.empty(self.n, dtype=torch.float32, device=dev)
+        _dev_f32(act, (self.n, 2), "act")
+        _dev_f32(obs, (self.n, self.d), "obs")
+        _dev_f32(reward, (self.n,), "reward")
+        check(lib().env_step_static(self.handle, _ptr(act), _ptr(obs), _ptr(reward),
+                                    _stream(stream)))
         return obs, reward
 
     def counts(self, stream=None):

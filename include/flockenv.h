@@ -392,7 +392,9 @@ void srv_destroy(srv_t *srv);
 int srv_submit(srv_t *srv, const env_params_t *p, const float *x, const float *y,
                const float *th, const float *s, int steps, int64_t *id);
 
-/* One serving tick: admit queued requests that now fit, run one closed-loop
+/* One serving tick: admit queued requests that now fit (in arrival order; a
+ * later request that fits may pass a waiting one, but once the head of the
+ * queue has waited 32 ticks nothing passes it until it is admitted), run one closed-loop
  * batched step over all running requests, retire those that finished.
  * *n_running / *agents receive the number of requests and agents stepped.
  * Synchronises the stream at the end of the tick. */

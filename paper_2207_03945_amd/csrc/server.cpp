@@ -80,6 +80,7 @@ struct Request {
     env_params_t p{};
     int steps = 0, done = 0;
     int state = 0;  // 0 queued, 1 running, 2 finished
+    int head_ticks = 0;  // ticks spent at the head of the queue without being admitted
     std::vector<float> x, y, th, s;
     std::vector<double> ret;
     env_t *env = nullptr;
@@ -202,11 +203,21 @@ int try_admit(srv_t *S, Request &r) {
     return ENV_OK;
 }
 
+// Ticks the head of the queue may be passed over by later requests that fit
+// before admission stops at it until it fits (it always fits eventually:
+// running requests finish in a bounded number of ticks and srv_submit
+// rejects requests larger than the arena).
+constexpr int kHeadPatience = 32;
+
 void admit_queued(srv_t *S) {
     for (auto it = S->queue.begin(); it != S->queue.end();) {
         Request &r = S->reqs.at(*it);
-        if (try_admit(S, r) == ENV_OK) it = S->queue.erase(it);
-        else ++it;
+        if (try_admit(S, r) == ENV_OK) {
+            it = S->queue.erase(it);
+            continue;
+        }
+        if (it == S->queue.begin() && ++r.head_ticks > kHeadPatience) break;  // hold for the head
+        ++it;
     }
 }
 
@@ -402,7 +413,12 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
     if (changed) {
         int64_t C;
         const int64_t G = running_agents(S, &C);
-        if (!S->running.empty()) resize_scratch(S, G, C, (int)S->running.size());
+        if (!S->running.empty()) {
+            resize_scratch(S, G, C, (int)S->running.size());
+        } else if (S->scratch.live) {  // an idle server holds no scratch: the arena is whole
+            S->alloc.release(S->scratch.off, S->scratch.bytes);
+            S->scratch.live = false;
+        }
         S->dirty = true;
     }
     return ENV_OK;

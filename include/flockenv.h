@@ -216,7 +216,8 @@ int env_step_static(env_t *env, const float *act, float *obs, float *reward, voi
  * Results are bitwise identical to stepping each env with env_step. */
 size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs);
 
-/* `ws` is device memory of >= env_batch_workspace_bytes bytes; the batch
+/* (The workspace also holds G next actions for env_step_policy.)
+ * `ws` is device memory of >= env_batch_workspace_bytes bytes; the batch
  * borrows the envs, which must outlive it.  Every env must have had
  * env_reset.  ENV_EINVAL (n_envs < 1, NULL env, mixed sectors or flags),
  * ENV_ENOMEM. */
@@ -316,7 +317,9 @@ int pol_sample(pol_t *pol, const float *obs, int64_t n, const float *log_std, co
  * launches of all steps are captured once into a HIP graph and replayed
  * (re-captured when an argument changes); `stream` must not be the null
  * stream.  Results equal `steps` rounds of pol_sample (or pol_forward) and
- * env_step_batched. */
+ * env_step_batched, bitwise.  For flock batches only the first action comes
+ * from a separate policy evaluation: each step's view sweep evaluates (and
+ * samples) the next step's action from the views it has just produced. */
 int env_rollout(env_batch_t *b, pol_t *pol, int steps, const float *log_std, const float *eps,
                 float *obs, float *act, float *logp, float *reward, void *stream);
 
@@ -342,10 +345,19 @@ int env_step_policy_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, float *act
 int rl_gae(int steps, int64_t n, float gamma, float lambda, const float *reward,
            const float *value, float *adv, float *ret, void *stream);
 
-/* Closed-loop batched step: act = policy(obs) for every agent, then one
+/* Closed-loop batched step (Sec. 4.3: one policy shared by all agents, each
+ * acting on its own view): act = policy(obs) for every agent, then one
  * batched step with those actions.  obs (device [G][d]) is read as the
  * current view and overwritten by the new one; act (device [G][2]) receives
- * the actions taken; reward (device [G]). */
+ * the actions taken; reward (device [G]).
+ * The policy runs inside the step's view sweep on the views it has just
+ * produced, still on chip, and the next step's actions are kept in the batch
+ * workspace: a following env_step_policy call with the same pol and obs
+ * pointer, with no env of the batch changed in between (by any other stepping
+ * call, env_set_state or env_reset), applies them without evaluating the
+ * policy again, so obs must not be written between such calls.  Otherwise
+ * (the first call, or after a change) the policy is evaluated on obs first.
+ * The actions are bitwise those of pol_forward on the same views. */
 int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
                     void *stream);
 

@@ -219,6 +219,7 @@ struct flock_env {
     DevEnv own[2];          // own tables: [b] has buffer b current
     int32_t base_host[2];   // {0, n}
     int parity = 0;         // index of the current record buffer
+    uint64_t gen = 0;       // bumped by every call that changes the state
     bool has_state = false;
     bool reset_done = false;
     bool uploaded = false;
@@ -273,6 +274,13 @@ struct flock_batch {
     GraphCache gc[2];                // K-step graphs by starting table
     GraphCache rgc[2];               // rollout graphs by starting table
     hipEvent_t events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // env_step_policy's next actions, computed inside its view sweep: valid
+    // for the next call with the same policy and obs while no env changed.
+    float2 *act_next = nullptr;      // [G] in the workspace
+    bool next_valid = false;
+    const void *next_pol = nullptr;
+    const float *next_obs = nullptr;
+    std::vector<uint64_t> next_gen;
 };
 
 namespace flock {
@@ -327,12 +335,16 @@ const env_params_t &env_params(const env_t *env) { return env->p; }
 
 int env_parity(const env_t *env) { return env->parity; }
 
-void env_advance(env_t *env, int steps) { env->parity ^= (steps & 1); }
+void env_advance(env_t *env, int steps) {
+    env->parity ^= (steps & 1);
+    ++env->gen;
+}
 
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s) {
     const int n = env->p.n_agents;
     env->has_state = true;
+    ++env->gen;
     if (n == 0) return ENV_OK;
     // Stage the agent-order arrays in the next buffer's record area (free
     // until the next step) and load them into the current buffer.
@@ -346,6 +358,21 @@ int env_load_host_state(env_t *env, const float *x, const float *y, const float 
         e = launch_load_state(stage, stage + n, stage + 2 * (size_t)n, stage + 3 * (size_t)n,
                               env->lay.rec[env->parity], env->lay.id[env->parity], n, s);
     if (e != hipSuccess) return hip_fail(e, "state upload");
+    return ENV_OK;
+}
+
+int env_reset_policy(env_t *env, float *obs, const PolFuse &pf, hipStream_t s) {
+    if (!env->has_state) return set_error(ENV_ESTATE, "reset before the state is loaded");
+    const int n = env->p.n_agents;
+    int rc = upload_own(env, s);
+    if (rc != ENV_OK) return rc;
+    hipError_t e = launch_zero_f64(env->lay.ret[env->parity], n, s);
+    if (e == hipSuccess) e = launch_step(env->plan, env->parity, 0, nullptr, obs, nullptr, 0, s,
+                                         nullptr, &pf);
+    if (e != hipSuccess) return hip_fail(e, "reset with the policy");
+    if (n > 0) env->parity ^= 1;
+    env->reset_done = true;
+    ++env->gen;
     return ENV_OK;
 }
 
@@ -483,6 +510,7 @@ int env_set_state(env_t *env, const float *x, const float *y, const float *th, c
                                      env->lay.id[env->parity], n, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_set_state");
     env->has_state = true;
+    ++env->gen;
     return ENV_OK;
 }
 
@@ -513,6 +541,7 @@ int env_reset(env_t *env, float *obs, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "env_reset: sense");
     if (n > 0) env->parity ^= 1;
     env->reset_done = true;
+    ++env->gen;
     return ENV_OK;
 }
 
@@ -524,6 +553,7 @@ int env_step(env_t *env, const float *act, float *obs, float *reward, void *stre
     hipError_t e = launch_step(env->plan, env->parity, 1, act, obs, reward, 1, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_step");
     if (n > 0) env->parity ^= 1;
+    ++env->gen;
     return ENV_OK;
 }
 
@@ -624,6 +654,7 @@ int env_step_static(env_t *env, const float *act, float *obs, float *reward, voi
     if (e == hipSuccess) e = launch_step(p, env->parity, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_static");
     env->parity ^= 1;
+    ++env->gen;
     return ENV_OK;
 }
 
@@ -665,7 +696,7 @@ size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs) {
     int64_t G, C;
     int v;
     if (batch_layout(envs, n_envs, nullptr, nullptr, &G, &C, &v) != ENV_OK) return 0;
-    return sort_scratch_bytes(G, C, n_envs);
+    return sort_scratch_bytes(G, C, n_envs) + align_up((size_t)G * sizeof(float2), 256);
 }
 
 static int batch_auto_lanes(const std::vector<env_t *> &envs) {
@@ -699,6 +730,7 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     }
     Carver cv{static_cast<char *>(ws), 0};
     carve_sort(cv, G, C, n_envs, &b->plan.a);
+    b->act_next = cv.take<float2>((size_t)G);
     if (bytes < align_up(cv.off, 256)) {
         delete b;
         return fail(ENV_ENOMEM, "batch workspace has %zu bytes, needs %zu", bytes,
@@ -804,7 +836,11 @@ static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
 // Every env of the batch swapped buffers `steps` times (empty envs too, so
 // the parities of a batch stay in step).
 static void batch_advance(env_batch_t *b, int steps) {
-    for (env_t *e : b->envs) e->parity ^= (steps & 1);
+    for (env_t *e : b->envs) {
+        e->parity ^= (steps & 1);
+        ++e->gen;
+    }
+    b->next_valid = false;
 }
 
 int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward, void *stream) {
@@ -944,13 +980,23 @@ static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, co
                 le = policy_launch_typed(pol, b->plan, tk, 0, o_k, e_k, ls, a_k, l_k, s);
                 if (le == hipSuccess)
                     le = policy_launch_typed(chaser, b->plan, tk, 1, o_k, e_k, ls + 2, a_k, l_k, s);
-            } else {
+            } else if (k == 0) {
+                // the first action; each step's view sweep then computes the next
                 le = eps ? policy_launch_sample(pol, o_k, G, e_k, ls, a_k, l_k, s)
                          : policy_launch(pol, o_k, G, a_k, s);
             }
+            PolFuse pf{};
+            const bool fuse = !tag && k + 1 < steps;
+            if (fuse) {
+                pf = policy_fuse_args(pol);
+                pf.act = reinterpret_cast<float2 *>(act + (size_t)(k + 1) * G * 2);
+                if (eps)
+                    policy_fuse_sampling(&pf, ls, eps + (size_t)(k + 1) * G * 2,
+                                         logp ? logp + (size_t)(k + 1) * G : nullptr);
+            }
             if (le == hipSuccess)
                 le = launch_step(b->plan, tk, 1, a_k, obs + (size_t)(k + 1) * G * d,
-                                 reward + (size_t)k * G, 1, s);
+                                 reward + (size_t)k * G, 1, s, nullptr, fuse ? &pf : nullptr);
         }
         return le;
     });
@@ -1009,13 +1055,30 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
         return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(pol),
                     b->plan.obs_dim);
     hipStream_t s = as_stream(stream);
+    bool have_next = b->next_valid && b->next_pol == policy_weights(pol) && b->next_obs == obs;
+    for (size_t k = 0; k < b->envs.size() && have_next; ++k)
+        have_next = b->envs[k]->gen == b->next_gen[k];
     int t;
     int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
-    hipError_t e = policy_launch(pol, obs, b->plan.G, act, s);
-    if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
-    if (e != hipSuccess) return hip_fail(e, "env_step_policy");
+    float *nxt = reinterpret_cast<float *>(b->act_next);
+    hipError_t e = hipSuccess;
+    if (!have_next) e = policy_launch(pol, obs, b->plan.G, nxt, s);
+    // the step applies the actions in act_next (copying them to act) and its
+    // view sweep writes the next step's actions there
+    PolFuse pf = policy_fuse_args(pol);
+    pf.act = b->act_next;
+    if (e == hipSuccess) e = launch_step(b->plan, t, 1, nxt, obs, reward, 1, s, nullptr, &pf, act);
+    if (e != hipSuccess) {
+        b->next_valid = false;
+        return hip_fail(e, "env_step_policy");
+    }
     batch_advance(b, 1);
+    b->next_valid = b->plan.G > 0;
+    b->next_pol = policy_weights(pol);
+    b->next_obs = obs;
+    b->next_gen.resize(b->envs.size());
+    for (size_t k = 0; k < b->envs.size(); ++k) b->next_gen[k] = b->envs[k]->gen;
     return ENV_OK;
 }
 

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "flockenv.h"
+#include "policy_tile.h"
 
 namespace flock {
 
@@ -72,6 +73,24 @@ struct SortArrays {
     int32_t *base;     // [E + 1] agent_base of each env, then G
 };
 
+// The shared policy evaluated inside a step's view sweep, on the view the
+// sweep has just produced (still on chip): each agent's next action, written
+// to `act` (batch rows [G][2]) or, when `act` is null, to each env's own
+// action rows (DevEnv::act).  mode 1: the mean action; mode 2: a Gaussian
+// sample round it with the draws `eps` (batch rows) and the log density into
+// `logp` (batch rows, may be null).  The actions are bitwise those of
+// policy_launch / policy_launch_sample on the same view.
+struct PolFuse {
+    PolLayout P;
+    int in_dim, kc;  // input length (the view row length), chunks of 32 inputs
+    int mode;
+    float max_turn, max_dspeed;
+    float2 *act;
+    const float2 *eps;
+    float sig0, sig1, logp_c;  // exp(log_std), -(log_std0 + log_std1) - log(2 pi)
+    float *logp;
+};
+
 // Launch plan of one step over a fixed set of envs.
 struct StepPlan {
     SortArrays a;
@@ -126,9 +145,13 @@ hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1
 // act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]); when NULL the
 // kernels use each env's own act/obs/rew rows from its descriptor.
 // add_return = 1 adds the reward to the FP64 returns.
+// pf (not null): the policy runs in the sweep (see PolFuse); tag plans excluded.
+// act_copy (not null, batch rows [G][2]): the move also writes each applied
+// action (as read, before its clamp) there.
 hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
                        float *reward, int add_return, hipStream_t s,
-                       hipEvent_t *phase_events = nullptr);
+                       hipEvent_t *phase_events = nullptr, const PolFuse *pf = nullptr,
+                       float *act_copy = nullptr);
 // The step's phases, in order.  Data they share: move writes tmp/key/slot and
 // the counts and reads the current records; scan turns counts into starts;
 // scatter writes the next records, sxy and stype; sweep reads those and the
@@ -136,7 +159,7 @@ hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *a
 enum StepPhase { kPhaseMove = 0, kPhaseScan = 1, kPhaseScatter = 2, kPhaseSweep = 3 };
 hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_move,
                         const float *act, float *obs, float *reward, int add_return,
-                        hipStream_t s);
+                        hipStream_t s, const PolFuse *pf = nullptr, float *act_copy = nullptr);
 // Load an agent-order state into buffer `rec`/`id` (identity order).
 hipError_t launch_load_state(const float *x, const float *y, const float *th, const float *sp,
                              float4 *rec, int32_t *id, int n, hipStream_t s);
@@ -171,6 +194,8 @@ void env_advance(env_t *env, int steps);        // record `steps` stepped elsewh
 // Copy a host state into the env (async on s; host arrays must outlive the copy).
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s);
+// env_reset whose view sweep also runs the policy (pf) on the initial view.
+int env_reset_policy(env_t *env, float *obs, const PolFuse &pf, hipStream_t s);
 // Device FP64 returns of the env in agent order, into `out` (device [n]).
 int env_returns_to(env_t *env, double *out, hipStream_t s);
 // Bytes of the batch sort scratch for G agents, C cells, E envs.
@@ -183,6 +208,10 @@ hipError_t policy_launch(const pol_t *pol, const float *obs, int64_t n, float *a
 // env's own rows (DevEnv::obs / DevEnv::act) of descriptor table `table`.
 hipError_t policy_launch_envs(const pol_t *pol, const StepPlan &plan, int table, hipStream_t s);
 int policy_in_dim(const pol_t *pol);
+// The actor's arguments for a fused step (mode 1, mean action, act = null).
+PolFuse policy_fuse_args(const pol_t *pol);
+// pf with Gaussian sampling (mode 2) as policy_launch_sample.
+void policy_fuse_sampling(PolFuse *pf, const float log_std[2], const float *eps, float *logp);
 int policy_is_critic(const pol_t *pol);
 // Device address of the policy's weights (identifies what a captured graph reads).
 const void *policy_weights(const pol_t *pol);

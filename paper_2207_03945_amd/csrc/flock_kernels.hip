@@ -222,7 +222,8 @@ constexpr int kMoveRecs = 1;
 
 __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEnv *__restrict__ envs,
                                                        int n_envs, int G, int do_move,
-                                                       const float2 *__restrict__ act) {
+                                                       const float2 *__restrict__ act,
+                                                       float2 *__restrict__ act_copy) {
     constexpr int R = kMoveRecs;
     __shared__ int s_env;
     __shared__ int s_kmin[kBlock / 64], s_kmax[kBlock / 64];
@@ -258,6 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
             if (!live[r]) continue;
             const DevEnv &E = envs[env[r]];
             av[r] = act ? act[E.agent_base + id[r]] : reinterpret_cast<const float2 *>(E.act)[id[r]];
+            if (act_copy) act_copy[E.agent_base + id[r]] = av[r];
         }
     }
 #pragma unroll
@@ -525,7 +527,8 @@ constexpr int kEnvRegR = 8;
 template <int R>
 __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv *__restrict__ envs,
                                                      int n_envs, int C, int do_move,
-                                                     const float2 *__restrict__ act, int tag) {
+                                                     const float2 *__restrict__ act, int tag,
+                                                     float2 *__restrict__ act_copy) {
     extern __shared__ int s_cells[];  // [Ce] counts, then starts within the env
     __shared__ int s_wave[kEnvNT / 64 + 1];
     const int tid = threadIdx.x;
@@ -550,6 +553,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
             if (do_move) {
                 const float2 av =
                     act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+                if (act_copy) act_copy[base + id] = av;
                 m = move_record(E, m, av);
             }
             if constexpr (kRegs) {
@@ -870,13 +874,32 @@ static_assert(kFlatUnroll <= kSortPad + 1 && kUnrollMax * 64 <= kSortPad + 1,
 // kFov: some env of the launch has a limited field of view.  obs rows hold
 // obs_dim floats: the v sectors, then the speed when obs_dim > v.
 // kM > 0: full view with v = 8 kM sectors (sector_oct); 0: any v.
-template <int NT, int G, bool kFov, bool kTag, int kM>
+//
+// kPol (1 mean action, 2 Gaussian sample; not with kTag): the shared policy
+// runs on the views the block has just produced, still in LDS, and writes each
+// agent's next action (PolFuse).  The views replace the minima in LDS, the
+// block's agents are cut into 16-agent tiles spread over its waves, and each
+// tile goes through mlp_tile as in the policy kernels.  LDS after the minima:
+// the network constants, per-agent speed / env / id, one hidden tile per wave.
+struct SweepPolLds {
+    int pc, speed, env, id, hid, words;  // offsets in 32-bit words from the minima's start
+};
+__host__ __device__ constexpr SweepPolLds sweep_pol_lds(int min_words, int A, int NT) {
+    const int pc = (min_words + 3) & ~3;
+    const int speed = pc + (int)((sizeof(PolConsts) + 15) / 16) * 4;
+    const int env = speed + A, id = env + A;
+    const int hid = (id + A + 3) & ~3;
+    return SweepPolLds{pc, speed, env, id, hid, hid + (NT / 64) * 16 * kHidLd / 2};
+}
+
+template <int NT, int G, bool kFov, bool kTag, int kM, int kPol = 0>
 __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__restrict__ envs,
                                               int n_envs, int Gtot, int v, int obs_dim,
                                               float *__restrict__ obs, float *__restrict__ reward,
-                                              int add_ret) {
+                                              int add_ret, PolFuse pf) {
+    static_assert(kPol == 0 || !kTag, "the fused policy serves flock envs");
     constexpr int A = NT / G;
-    extern __shared__ uint32_t s_min[];  // [channels * v][A]
+    extern __shared__ uint32_t s_min[];  // [channels * v][A] (then the policy's, kPol)
     const int vs = kTag ? 2 * v : v;     // minima per agent
     __shared__ int s_env;
     const int tid = threadIdx.x, slot = tid / G, li = tid % G;
@@ -885,9 +908,15 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     uint32_t *smin = s_min + slot;
     if constexpr (G > 1)
         for (int k = li; k < vs; k += G) smin[k * A] = kInfBits;
+    const SweepPolLds PL = sweep_pol_lds(vs * A, A, NT);
+    PolConsts *s_pc = reinterpret_cast<PolConsts *>(s_min + PL.pc);
+    float *s_speed = reinterpret_cast<float *>(s_min + PL.speed);
+    int *s_pe = reinterpret_cast<int *>(s_min + PL.env);
+    int *s_pid = reinterpret_cast<int *>(s_min + PL.id);
+    if constexpr (kPol != 0) load_pol_consts(pf.P, s_pc, tid, NT);
     __syncthreads();
     const int pos = p0 + slot;
-    if constexpr (G == 1) {
+    if constexpr (G == 1 && kPol == 0) {
         if (pos >= Gtot) return;
     }
     // G > 1: every lane reaches the second barrier; a group is active or not as a whole
@@ -1035,7 +1064,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
 
     if constexpr (G > 1) {
         __syncthreads();  // the group's minima are complete
-        if (!active) return;
+        if (kPol == 0 && !active) return;
 #pragma unroll
         for (int m = G / 2; m >= 1; m >>= 1) {
             nb += __shfl_xor(nb, m, 64);
@@ -1043,42 +1072,93 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         }
     }
     constexpr bool kGl = G > 1;
-    const int id = load_as<kGl>(E.id_nxt, j);
-    const float inv_r = E.inv_radius;
-    float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
-    if (li == 0 && obs_dim > vs) store_as<kGl>(orow, vs, me.w);  // speed after the move (Sec. 4.1)
-    if constexpr (G > 1) {
-        for (int k = li; k < vs; k += G) {
-            const uint32_t m = smin[k * A];
-            store_as<kGl>(orow, k,
-                          m == kInfBits ? 0.0f
-                                        : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r);
-        }
-    } else if ((obs_dim & 3) == 0 && (vs & 3) == 0) {
-        for (int k = 0; k < vs; k += 4) {
-            float o[4];
+    // A view value from a sector minimum; with kPol it also replaces the minimum in LDS.
+    auto view = [&](int k, float inv_r) {
+        const uint32_t m = smin[k * A];
+        const float o = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
+        if constexpr (kPol != 0) smin[k * A] = __float_as_uint(o);
+        return o;
+    };
+    if (active) {
+        const int id = load_as<kGl>(E.id_nxt, j);
+        const float inv_r = E.inv_radius;
+        float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
+        if (li == 0 && obs_dim > vs) store_as<kGl>(orow, vs, me.w);  // speed after the move (Sec. 4.1)
+        if constexpr (G > 1) {
+            for (int k = li; k < vs; k += G) store_as<kGl>(orow, k, view(k, inv_r));
+        } else if ((obs_dim & 3) == 0 && (vs & 3) == 0) {
+            for (int k = 0; k < vs; k += 4) {
+                float o[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t m = smin[(k + u) * A];
-                o[u] = m == kInfBits ? 0.0f
-                                     : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
+                for (int u = 0; u < 4; ++u) o[u] = view(k + u, inv_r);
+                *reinterpret_cast<float4 *>(orow + k) = make_float4(o[0], o[1], o[2], o[3]);
             }
-            *reinterpret_cast<float4 *>(orow + k) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+            for (int k = 0; k < vs; ++k) orow[k] = view(k, inv_r);
         }
-    } else {
-        for (int k = 0; k < vs; ++k) {
-            const uint32_t m = smin[k * A];
-            orow[k] = m == kInfBits ? 0.0f : 1.0f - __builtin_amdgcn_sqrtf(__uint_as_float(m)) * inv_r;
+        if (li == 0) {
+            const float r =
+                (kTag && ti) ? E.r_catch * (float)col : E.r_nb * (float)nb + E.r_col * (float)col;
+            if (reward) reward[E.agent_base + id] = r;
+            else if (E.rew) store_as<kGl>(E.rew, id, r);
+            if (add_ret) store_as<kGl>(E.ret_nxt, j, load_as<kGl>(E.ret_nxt, j) + (double)r);
+            if (E.nb) {
+                store_as<kGl>(E.nb, id, nb);
+                store_as<kGl>(E.col, id, col);
+            }
+            if constexpr (kPol != 0) {
+                s_speed[slot] = me.w;
+                s_pe[slot] = e;
+                s_pid[slot] = id;
+            }
         }
+    } else if constexpr (kPol != 0) {
+        if (li == 0) s_pe[slot] = -1;
     }
-    if (li != 0) return;
-    const float r = (kTag && ti) ? E.r_catch * (float)col : E.r_nb * (float)nb + E.r_col * (float)col;
-    if (reward) reward[E.agent_base + id] = r;
-    else if (E.rew) store_as<kGl>(E.rew, id, r);
-    if (add_ret) store_as<kGl>(E.ret_nxt, j, load_as<kGl>(E.ret_nxt, j) + (double)r);
-    if (E.nb) {
-        store_as<kGl>(E.nb, id, nb);
-        store_as<kGl>(E.col, id, col);
+    if constexpr (kPol != 0) {
+        __syncthreads();  // every agent's view, speed and row are in LDS
+        constexpr int kTiles = (A + 15) / 16;
+        const int wid = tid >> 6, lane = tid & 63, g = lane >> 4, colx = lane & 15;
+        __bf16 *s_hid = reinterpret_cast<__bf16 *>(s_min + PL.hid) + (size_t)wid * 16 * kHidLd;
+        if (wid >= kTiles) return;
+        for (int tile = wid; tile < kTiles; tile += NT / 64) {
+            const int sl = tile * 16 + colx;
+            const int pe = sl < A ? s_pe[sl] : -1;
+            const bool valid = pe >= 0;
+            // inputs 32 c + 8 g .. + 7 of agent sl: the view, then the speed when
+            // the row carries it, zero beyond
+            auto xb = [&](int c) {
+                bf16x8 x;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int k = 32 * c + 8 * g + jj;
+                    float o = 0.0f;
+                    if (valid) {
+                        if (k < vs) o = __uint_as_float(s_min[k * A + sl]);
+                        else if (k == vs && obs_dim > vs) o = s_speed[sl];
+                    }
+                    x[jj] = (__bf16)o;
+                }
+                return x;
+            };
+            // weights read at use (they stay in the vector L1 cache): held in
+            // registers they would lower the whole kernel's occupancy
+            auto w1a = [&](int c, int t) { return pf.P.w1[(c * 4 + t) * 64 + lane]; };
+            auto w2a = [&](int c, int t) { return pf.P.w2[(c * 4 + t) * 64 + lane]; };
+            const float2 z = mlp_tile(pf.kc, xb, w1a, w2a, *s_pc, s_hid, lane);
+            if (g == 0 && valid) {
+                const DevEnv &Ej = envs[pe];
+                const int idj = s_pid[sl];
+                const int64_t row = (int64_t)Ej.agent_base + idj;
+                const float2 ev = kPol == 2 ? pf.eps[row] : make_float2(0.0f, 0.0f);
+                const float2 av =
+                    pol_output<kPol == 2>(z, *s_pc, pf.max_turn, pf.max_dspeed, ev, pf.sig0,
+                                          pf.sig1, pf.logp_c,
+                                          (kPol == 2 && pf.logp) ? pf.logp + row : nullptr);
+                if (pf.act) pf.act[row] = av;
+                else reinterpret_cast<float2 *>(Ej.act)[idj] = av;
+            }
+        }
     }
 }
 
@@ -1189,38 +1269,50 @@ hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
 }
 
 namespace {
-template <int NT, int G, bool kFov, bool kTag, int kM = 0>
+template <int NT, int G, bool kFov, bool kTag, int kM = 0, int kPol = 0>
 void launch_sweep_v(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
-                    int add_return, hipStream_t s) {
+                    int add_return, hipStream_t s, const PolFuse *pf) {
     constexpr int A = NT / G;
-    const size_t lds = (size_t)(kTag ? 2 : 1) * p.v * A * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag, kM>), dim3(blocks_for(Gtot, A)), dim3(NT), lds,
-                       s, p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return);
+    const int min_words = (kTag ? 2 : 1) * p.v * A;
+    const size_t lds = (size_t)(kPol ? sweep_pol_lds(min_words, A, NT).words : min_words) *
+                       sizeof(uint32_t);
+    hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag, kM, kPol>), dim3(blocks_for(Gtot, A)), dim3(NT),
+                       lds, s, p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return,
+                       pf ? *pf : PolFuse{});
+}
+
+// Flock plans: the view variant (limited view, or 8 / 16 / 32 sectors without
+// the arctangent) and, with pf, the fused policy's output mode.
+template <int NT, int G, int kPol>
+void launch_sweep_flock(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
+                        int add_return, hipStream_t s, const PolFuse *pf) {
+    if (p.fov) launch_sweep_v<NT, G, true, false, 0, kPol>(p, envs, Gtot, obs, reward, add_return, s, pf);
+    else if (p.v == 8) launch_sweep_v<NT, G, false, false, 1, kPol>(p, envs, Gtot, obs, reward, add_return, s, pf);
+    else if (p.v == 16) launch_sweep_v<NT, G, false, false, 2, kPol>(p, envs, Gtot, obs, reward, add_return, s, pf);
+    else if (p.v == 32) launch_sweep_v<NT, G, false, false, 4, kPol>(p, envs, Gtot, obs, reward, add_return, s, pf);
+    else launch_sweep_v<NT, G, false, false, 0, kPol>(p, envs, Gtot, obs, reward, add_return, s, pf);
 }
 
 template <int NT, int G>
 void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
-                  int add_return, hipStream_t s) {
+                  int add_return, hipStream_t s, const PolFuse *pf) {
     if (p.tag) {
-        if (p.fov) launch_sweep_v<NT, G, true, true>(p, envs, Gtot, obs, reward, add_return, s);
-        else launch_sweep_v<NT, G, false, true>(p, envs, Gtot, obs, reward, add_return, s);
-    } else if (p.fov) {
-        launch_sweep_v<NT, G, true, false>(p, envs, Gtot, obs, reward, add_return, s);
-    } else if (p.v == 8) {
-        launch_sweep_v<NT, G, false, false, 1>(p, envs, Gtot, obs, reward, add_return, s);
-    } else if (p.v == 16) {
-        launch_sweep_v<NT, G, false, false, 2>(p, envs, Gtot, obs, reward, add_return, s);
-    } else if (p.v == 32) {
-        launch_sweep_v<NT, G, false, false, 4>(p, envs, Gtot, obs, reward, add_return, s);
+        if (p.fov) launch_sweep_v<NT, G, true, true>(p, envs, Gtot, obs, reward, add_return, s, nullptr);
+        else launch_sweep_v<NT, G, false, true>(p, envs, Gtot, obs, reward, add_return, s, nullptr);
+    } else if (!pf) {
+        launch_sweep_flock<NT, G, 0>(p, envs, Gtot, obs, reward, add_return, s, nullptr);
+    } else if (pf->mode == 2) {
+        launch_sweep_flock<NT, G, 2>(p, envs, Gtot, obs, reward, add_return, s, pf);
     } else {
-        launch_sweep_v<NT, G, false, false>(p, envs, Gtot, obs, reward, add_return, s);
+        launch_sweep_flock<NT, G, 1>(p, envs, Gtot, obs, reward, add_return, s, pf);
     }
 }
 }  // namespace
 
 hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_move,
                         const float *act, float *obs, float *reward, int add_return,
-                        hipStream_t s) {
+                        hipStream_t s, const PolFuse *pf, float *act_copy) {
+    if (pf && p.tag) return hipErrorInvalidValue;  // the fused policy serves flock plans
     if (p.G == 0) return hipSuccess;
     const int G = (int)p.G, C = (int)p.C;
     const DevEnv *envs = p.a.envs[table & 1];
@@ -1230,18 +1322,20 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
             if (p.env_sort_recs > 0) {
                 const size_t lds = (size_t)p.max_env_cells * sizeof(int);
                 const float2 *a2 = reinterpret_cast<const float2 *>(act);
+                float2 *ac2 = reinterpret_cast<float2 *>(act_copy);
                 const dim3 grid(p.n_envs), block(kEnvNT);
                 switch (p.env_sort_recs) {
-                    case 2: hipLaunchKernelGGL(k_env_sort<2>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
-                    case 4: hipLaunchKernelGGL(k_env_sort<4>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
-                    case 8: hipLaunchKernelGGL(k_env_sort<8>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
-                    default: hipLaunchKernelGGL(k_env_sort<16>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag); break;
+                    case 2: hipLaunchKernelGGL(k_env_sort<2>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag, ac2); break;
+                    case 4: hipLaunchKernelGGL(k_env_sort<4>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag, ac2); break;
+                    case 8: hipLaunchKernelGGL(k_env_sort<8>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag, ac2); break;
+                    default: hipLaunchKernelGGL(k_env_sort<16>, grid, block, lds, s, p.a, envs, p.n_envs, C, do_move, a2, p.tag, ac2); break;
                 }
                 break;
             }
             hipLaunchKernelGGL(k_move_count, dim3(blocks_for(G, kBlock * kMoveRecs)), dim3(kBlock),
                                0, s, p.a, envs, p.n_envs, G, do_move,
-                               reinterpret_cast<const float2 *>(act));
+                               reinterpret_cast<const float2 *>(act),
+                               reinterpret_cast<float2 *>(act_copy));
             break;
         case kPhaseScan:
             if (p.env_sort_recs > 0) break;  // done inside k_env_sort
@@ -1273,12 +1367,12 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
             break;
         case kPhaseSweep: {
             const int lanes = p.lanes;
-            if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s);
-            else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s);
-            else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s);
+            if (lanes == 4) launch_sweep<256, 4>(p, envs, G, obs, reward, add_return, s, pf);
+            else if (lanes == 16) launch_sweep<256, 16>(p, envs, G, obs, reward, add_return, s, pf);
+            else if (lanes == 64) launch_sweep<256, 64>(p, envs, G, obs, reward, add_return, s, pf);
             else if ((p.tag ? 2 * p.v : p.v) <= 32)
-                launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s);
-            else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s);
+                launch_sweep<256, 1>(p, envs, G, obs, reward, add_return, s, pf);
+            else launch_sweep<64, 1>(p, envs, G, obs, reward, add_return, s, pf);
             break;
         }
     }
@@ -1286,13 +1380,15 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
 }
 
 hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
-                       float *reward, int add_return, hipStream_t s, hipEvent_t *ev) {
+                       float *reward, int add_return, hipStream_t s, hipEvent_t *ev,
+                       const PolFuse *pf, float *act_copy) {
     if (p.G == 0) return hipSuccess;
     const StepPhase order[4] = {kPhaseMove, kPhaseScan, kPhaseScatter, kPhaseSweep};
     hipError_t e = hipSuccess;
     for (int k = 0; k < 4 && e == hipSuccess; ++k) {
         if (ev) (void)hipEventRecord(ev[k], s);
-        e = launch_phase(p, table, order[k], do_move, act, obs, reward, add_return, s);
+        e = launch_phase(p, table, order[k], do_move, act, obs, reward, add_return, s, pf,
+                         act_copy);
     }
     if (ev) (void)hipEventRecord(ev[4], s);
     return e;

@@ -9,15 +9,10 @@
 // products accumulated in FP32 by v_mfma_f32_16x16x32_bf16, biases and the
 // 64 -> 2 output layer in FP32 on the vector ALUs (with BF16-rounded weights).
 //
-// Layout.  One wave handles 16 agents per tile and computes the transposed
-// products H1^T = W1^T X^T and H2^T = W2^T H1^T (hidden units as MFMA rows,
-// agents as columns).  Lane l = 16 g + col holds agent col; in register r of
-// output tile t (hidden units 16 t .. 16 t + 15) it holds unit 16 t + 4 g + r,
-// and as a B operand it supplies the eight K values 32 c + 8 g .. + 7 of chunk
-// c.  Layer 1's results reach layer 2 through a per-wave LDS tile of BF16
-// hidden rows; the weights are packed into A-operand lane order once on the
-// host (pol_create).  Small tiles keep the tanh work per lane low (16 values
-// per layer) and give a batch many tiles to spread over the CUs.
+// Layout: see policy_tile.h (one wave per 16-agent tile, hidden units as MFMA
+// rows, layer 1 -> layer 2 through a per-wave LDS tile).  Small tiles keep the
+// tanh work per lane low (16 values per layer) and give a batch many tiles to
+// spread over the CUs.
 
 #include <math.h>
 #include <string.h>
@@ -26,29 +21,14 @@
 #include <vector>
 
 #include "flock_internal.h"
+#include "policy_tile.h"
 
 namespace flock {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
-constexpr int kHidden = 64;
 constexpr int kPolBlock = 256;
 constexpr int kMaxIn = 257;                    // 256 sectors + speed
-
-// Device workspace of one policy.
-struct PolLayout {
-    // A operands, lane (g = l / 16, col = l % 16), element j of chunk c, tile t:
-    bf16x8 *w1;  // [kc][4 tiles][64 lanes]  W1[32 c + 8 g + j][16 t + col] (0 beyond in_dim)
-    bf16x8 *w2;  // [2][4 tiles][64 lanes]   W2[32 c + 8 g + j][16 t + col]
-    float *b1;   // [64] by hidden unit
-    float *b2;   // [64]
-    float *w3;   // [2 outputs][64] (BF16-rounded)
-    float *b3;   // [2]
-    size_t bytes;
-};
 
 // kc: chunks of 32 inputs.
 PolLayout carve_pol(char *base, int kc) {
@@ -62,12 +42,6 @@ PolLayout carve_pol(char *base, int kc) {
     l.b3 = cv.take<float>(2);
     l.bytes = align_up(cv.off, 256);
     return l;
-}
-
-__device__ __forceinline__ float tanh_fast(float x) {
-    x = fminf(fmaxf(x, -15.0f), 15.0f);
-    const float e = __expf(2.0f * x);
-    return __fdividef(e - 1.0f, e + 1.0f);
 }
 
 // Last env e with base[e] <= row.
@@ -115,7 +89,6 @@ constexpr int kStageLoads = 8;
 // its tile's 16 consecutive rows, one contiguous block of 16 in_dim floats,
 // into LDS as BF16 (zero beyond in_dim) with coalesced 16-byte loads, and the
 // MFMA operands are read from there; otherwise every lane loads its own row.
-constexpr int kHidLd = 72;  // BF16 per agent row of the hidden tile (64 + 8 pad)
 
 template <bool kLdsW1, int kOut, bool kStage>
 __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, int kc,
@@ -125,7 +98,7 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                                                       const DevEnv *__restrict__ envs,
                                                       const int32_t *__restrict__ base,
                                                       int n_envs, OutArgs oa) {
-    __shared__ float s_b1[64], s_b2[64], s_w3[128], s_b3[2];
+    __shared__ PolConsts s_pc;
     extern __shared__ bf16x8 s_dyn[];
     const int wid = threadIdx.x / 64;
     bf16x8 *s_w1 = s_dyn;  // [kc][4 tiles][64 lanes] when kLdsW1
@@ -137,12 +110,7 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                     (size_t)(kPolBlock / 64) * 16 * kHidLd + (size_t)wid * 16 * ld;
     if (kLdsW1)
         for (int i = threadIdx.x; i < kc * 256; i += kPolBlock) s_w1[i] = P.w1[i];
-    for (int i = threadIdx.x; i < 64; i += kPolBlock) {
-        s_b1[i] = P.b1[i];
-        s_b2[i] = P.b2[i];
-    }
-    for (int i = threadIdx.x; i < 128; i += kPolBlock) s_w3[i] = P.w3[i];
-    if (threadIdx.x < 2) s_b3[threadIdx.x] = P.b3[threadIdx.x];
+    load_pol_consts(P, &s_pc, threadIdx.x, kPolBlock);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
@@ -224,78 +192,37 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             orow = E.obs + i * in_dim;
             arow = reinterpret_cast<float2 *>(E.act) + i;
         }
-        // layer 1: H1^T[16 t + i][agent] over K chunks of 32 inputs
-        f32x4 acc1[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
-        for (int c = 0; c < kc; ++c) {
-            bf16x8 xb;
+        // the tile's eight inputs 32 c + 8 g .. + 7 of agent col, as BF16
+        auto xb = [&](int c) {
+            bf16x8 x;
             const int k0 = 32 * c + 8 * g;
             if constexpr (kStage) {
-                xb = *reinterpret_cast<const bf16x8 *>(s_obs + col * ld + k0);
+                x = *reinterpret_cast<const bf16x8 *>(s_obs + col * ld + k0);
             } else if (valid && in_dim % 4 == 0 && k0 + 8 <= in_dim) {
                 const float4 *src = reinterpret_cast<const float4 *>(orow + k0);
                 const float4 u = src[0], w = src[1];
-                xb[0] = (__bf16)u.x; xb[1] = (__bf16)u.y; xb[2] = (__bf16)u.z; xb[3] = (__bf16)u.w;
-                xb[4] = (__bf16)w.x; xb[5] = (__bf16)w.y; xb[6] = (__bf16)w.z; xb[7] = (__bf16)w.w;
+                x[0] = (__bf16)u.x; x[1] = (__bf16)u.y; x[2] = (__bf16)u.z; x[3] = (__bf16)u.w;
+                x[4] = (__bf16)w.x; x[5] = (__bf16)w.y; x[6] = (__bf16)w.z; x[7] = (__bf16)w.w;
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int k = k0 + j;
-                    xb[j] = (__bf16)((valid && k < in_dim) ? orow[k] : 0.0f);
+                    x[j] = (__bf16)((valid && k < in_dim) ? orow[k] : 0.0f);
                 }
             }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const bf16x8 a = kLdsW1 ? s_w1[(c * 4 + t) * 64 + lane] : w1[t];
-                acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb, acc1[t], 0, 0, 0);
-            }
-        }
-        // bias + tanh, into the hidden tile as B operand rows of layer 2
-        __threadfence_block();  // the previous tile's reads of the hidden tile come first
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            __bf16 hv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                hv[r] = (__bf16)tanh_fast(acc1[t][r] + s_b1[16 * t + 4 * g + r]);
-            uint2 packed;
-            memcpy(&packed, hv, sizeof(packed));
-            *reinterpret_cast<uint2 *>(s_hid + col * kHidLd + 16 * t + 4 * g) = packed;
-        }
-        __threadfence_block();  // the wave's hidden tile before its reads
-        f32x4 acc2[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const bf16x8 hb = *reinterpret_cast<const bf16x8 *>(s_hid + col * kHidLd + 32 * c + 8 * g);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[c][t], hb, acc2[t], 0, 0, 0);
-        }
-        float z0 = 0.0f, z1 = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int h = 16 * t + 4 * g + r;
-                const float hv = tanh_fast(acc2[t][r] + s_b2[h]);
-                z0 = z0 + hv * s_w3[h];
-                z1 = z1 + hv * s_w3[64 + h];
-            }
-        z0 = z0 + __shfl_xor(z0, 16, 64);
-        z1 = z1 + __shfl_xor(z1, 16, 64);
-        z0 = z0 + __shfl_xor(z0, 32, 64);
-        z1 = z1 + __shfl_xor(z1, 32, 64);
+            return x;
+        };
+        auto w1a = [&](int c, int t) { return kLdsW1 ? s_w1[(c * 4 + t) * 64 + lane] : w1[t]; };
+        auto w2a = [&](int c, int t) { return w2[c][t]; };
+        const float2 z = mlp_tile(kc, xb, w1a, w2a, s_pc, s_hid, lane);
         if (g == 0 && valid) {
             if constexpr (kOut == kValue) {
-                oa.val[agent] = z0 + s_b3[0];
+                oa.val[agent] = z.x + s_pc.b3[0];
             } else {
-                float2 a = make_float2(max_turn * tanhf(z0 + s_b3[0]), max_dspeed * tanhf(z1 + s_b3[1]));
-                if constexpr (kOut == kSample) {
-                    const float2 e = oa.eps[agent];
-                    a.x = a.x + oa.sig0 * e.x;
-                    a.y = a.y + oa.sig1 * e.y;
-                    if (oa.logp) oa.logp[agent] = -0.5f * (e.x * e.x + e.y * e.y) + oa.logp_c;
-                }
-                *arow = a;
+                const float2 e = kOut == kSample ? oa.eps[agent] : make_float2(0.0f, 0.0f);
+                *arow = pol_output<kOut == kSample>(z, s_pc, max_turn, max_dspeed, e, oa.sig0,
+                                                   oa.sig1, oa.logp_c,
+                                                   oa.logp ? oa.logp + agent : nullptr);
             }
         }
     }
@@ -423,6 +350,26 @@ int policy_is_critic(const pol_t *p) { return p->critic; }
 const void *policy_weights(const pol_t *p) { return p->lay.w1; }
 
 int policy_in_dim(const pol_t *p) { return p->in_dim; }
+
+PolFuse policy_fuse_args(const pol_t *p) {
+    PolFuse f{};
+    f.P = p->lay;
+    f.in_dim = p->in_dim;
+    f.kc = p->kc;
+    f.mode = 1;
+    f.max_turn = p->max_turn;
+    f.max_dspeed = p->max_dspeed;
+    return f;
+}
+
+void policy_fuse_sampling(PolFuse *f, const float log_std[2], const float *eps, float *logp) {
+    f->mode = 2;
+    f->eps = reinterpret_cast<const float2 *>(eps);
+    f->sig0 = (float)exp((double)log_std[0]);
+    f->sig1 = (float)exp((double)log_std[1]);
+    f->logp_c = (float)(-((double)log_std[0] + (double)log_std[1]) - log(2.0 * M_PI));
+    f->logp = logp;
+}
 
 }  // namespace flock
 

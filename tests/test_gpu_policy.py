@@ -12,6 +12,8 @@ bound in FP64 for every agent and requires the GPU error to stay under it.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -148,3 +150,57 @@ def test_policy_staged_and_direct_loads_agree_bitwise(in_dim):
     b = pol.forward(shifted)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("kind,lanes", [("v16", 0), ("v16", 1), ("v16", 4), ("v16", 64),
+                                        ("v8", 16), ("paper129", 16), ("paper129", 1)])
+def test_fused_policy_step_equals_forward_then_step(kind, lanes):
+    """env_step_policy runs the policy inside the view sweep (the next step's
+    actions come from the views still on chip): over six steps its actions,
+    views and rewards equal pol_forward + env_step_batched bitwise, for each
+    sweep lane count and view kind; the cached next actions are recomputed
+    when the obs pointer changes and when an env's state is set anew."""
+    if kind == "paper129":
+        ps = [flock.Params(n_agents=n, box=100.0, radius=10.0, sectors=128,
+                           fov=math.radians(250.0), flags=flock.ENV_FLAG_SPEED_OBS)
+              for n in (900, 70)]
+        in_dim = 129
+    else:
+        v = 16 if kind == "v16" else 8
+        ps = [flock.Params(n_agents=n, box=b, sectors=v) for n, b in ((2500, 200.0), (333, 75.0))]
+        in_dim = v
+    pol, _, _ = make_policy(in_dim)
+    states = [workloads.uniform_state(p.n_agents, p.box, seed=k + 3) for k, p in enumerate(ps)]
+    pair = []
+    for _ in range(2):
+        envs = []
+        for p, st in zip(ps, states):
+            e = flock.Env(p)
+            e.set_state(*[torch.from_numpy(a).cuda() for a in st])
+            envs.append(e)
+        obs = torch.cat([e.reset() for e in envs]).contiguous()
+        b = flock.Batch(envs)
+        if lanes:
+            b.set_sweep_lanes(lanes)
+        pair.append((envs, b, obs))
+    (envs_a, ba, obs_a), (envs_b, bb, obs_b) = pair
+    G = ba.n
+    act_a = torch.empty(G, 2, device="cuda")
+    rew_a, rew_b = torch.empty(G, device="cuda"), torch.empty(G, device="cuda")
+    for t in range(6):
+        if t == 3:      # a new obs buffer: the policy is evaluated again
+            obs_a = obs_a.clone()
+        if t == 4:      # a state set anew on both sides
+            st = workloads.uniform_state(ps[1].n_agents, ps[1].box, seed=99)
+            for envs in (envs_a, envs_b):
+                envs[1].set_state(*[torch.from_numpy(a).cuda() for a in st])
+            off = ba.offsets
+            for envs, o in ((envs_a, obs_a), (envs_b, obs_b)):
+                o[off[1]:off[2]] = envs[1].reset()
+        ba.step_policy(pol, act_a, obs_a, rew_a)
+        act_b = pol.forward(obs_b)
+        bb.step(act_b, obs_b, rew_b)
+        torch.cuda.synchronize()
+        assert torch.equal(act_a, act_b), t
+        assert torch.equal(obs_a, obs_b), t
+        assert torch.equal(rew_a, rew_b), t

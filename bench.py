@@ -4,17 +4,24 @@
 Workload (the `value`): 200 independent 5,000-agent flock envs (periodic box
 of side 316, vision 8, collision 0.5, 16 sectors, seeded uniform actions
 turn in [-0.2, 0.2], dspeed in [-0.1, 0.1]) stepped together by one batched
-step; K steps replayed from one captured HIP graph, actions resident in HBM.
-A "step" is the whole step path: move + cell count, scan, scatter, sweep
-(view, reward, FP64 return) for every agent of every env.
+step; K steps replayed from one captured HIP graph, actions resident in HBM,
+timed with HIP events on the stream over five replays (the median is the
+value).  A "step" is the whole step path: move + cell count, scan, scatter,
+sweep (view, reward, FP64 return) for every agent of every env.
 
 Also reported on the same JSON line:
-  plain      one 5,000-agent env stepped alone (p50/p99 per-step latency)
+  plain      one 5,000-agent env stepped alone (eager per-step latency)
   flock50k   the 50,000-agent clustered env (64 blobs) and a uniform 50,000-agent
              env, plain and batched x20
-  roofline   the dominant kernel (the neighbour sweep), its algorithmic bytes
-             per launch over its average HIP-event duration on the stream
-  cpu_baseline  the CPU oracle on the host cores on a bounded sample
+  policy     the closed-loop step with the policy fused into the view sweep
+             against the policy launched separately before the step
+  serving    Poisson arrivals at 20/s for 60 s, then a sweep of arrival rates
+             up to saturation (p50/p99 tick latency, agent-steps/s per rate)
+  roofline   the dominant kernel (the neighbour sweep): the step's algorithmic
+             bytes (44 + 4v per agent-step) per launch over its average
+             HIP-event duration, against HBM
+  cpu_baseline  the CPU oracle on the host cores (and on one core) on a
+             bounded sample
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -38,6 +45,7 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 # clock (157.3 TFLOP/s counts an FMA as 2 and packed FP32 as 2 more; packed
 # FP32 is not generated here).
 VALU_PEAK = 256 * 64 * 2.4e9
+VALU_ISSUE_PEAK = 256 * 2.4e9   # wave64 VALU instructions per second (one per clock per CU)
 OPS_PER_CANDIDATE = 12     # image shift, d^2, radius and self tests, counts
 OPS_PER_NEIGHBOUR = 30     # bearing, sector, per-sector minimum
 V = 16                     # sectors of the paper-scale workloads
@@ -82,8 +90,9 @@ def device_actions(G, K, seed, tag=False):
     return a.contiguous()
 
 
-def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False):
-    """Graph-replayed K-step run + per-phase timing; returns a dict."""
+def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False, reps=5):
+    """Graph-replayed K-step runs (median of `reps`, HIP events on the stream),
+    graph-replayed one-step latencies, and per-phase timing; returns a dict."""
     import torch
     G = batch.n
     act = device_actions(G, K, seed, tag)
@@ -93,30 +102,43 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False):
     with torch.cuda.stream(stream):
         for t in range(W):
             batch.step(act[t % K], obs, rew[t % K], stream)
-        # per-step latency of eager batched steps + per-phase durations
+        # per-phase durations of eager steps
         phases = []
-        lat = []
         for t in range(timed_reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ph = batch.step_timed(act[t % K], obs, rew[t % K], stream)
-            e1.record(stream)
-            stream.synchronize()
-            lat.append(e0.elapsed_time(e1))
-            phases.append(ph)
-        batch.capture(K, act, obs, rew, stream)
+            phases.append(batch.step_timed(act[t % K], obs, rew[t % K], stream))
+        # per-step latency: a one-step graph replayed K times, each replay
+        # bracketed by events (back to back on the stream)
+        for _ in range(2):      # capture and launch both starting tables' graphs
+            batch.run(1, act[:1], obs, rew[:1], stream)
+        ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(K)]
+        for t in range(K):
+            ev1[t][0].record(stream)
+            batch.run(1, act[:1], obs, rew[:1], stream)
+            ev1[t][1].record(stream)
         stream.synchronize()
+        lat = [a.elapsed_time(b) for a, b in ev1]
+        # throughput: the K-step graph replayed `reps` times
+        for _ in range(2):      # both starting tables (K odd alternates them)
+            batch.run(K, act, obs, rew, stream)
+        evk = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        batch.run(K, act, obs, rew, stream)
+        for r in range(reps):
+            evk[r][0].record(stream)
+            batch.run(K, act, obs, rew, stream)
+            evk[r][1].record(stream)
         stream.synchronize()
-        t1 = time.perf_counter()
+        wall = time.perf_counter() - t0
     assert torch.isfinite(obs).all() and torch.isfinite(rew).all()
-    el = t1 - t0
+    runs_ms = [a.elapsed_time(b) for a, b in evk]
+    el = float(np.median(runs_ms)) * 1e-3
     ph = np.mean(np.asarray(phases), axis=0)
     return {"agent_steps_per_s": G * K / el, "ms_per_step": 1e3 * el / K, "agents": G,
+            "replay_ms": runs_ms, "replays_wall_s": wall,
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "latency_kind": "one-step graph replays, HIP events",
             "phase_ms": {"move_count": float(ph[0]), "scan": float(ph[1]),
                          "scatter": float(ph[2]), "sweep": float(ph[3])},
             "fused_sort": bool(ph[1] == 0 and ph[2] == 0)}
@@ -147,64 +169,136 @@ def bench_plain(env, n, K, W, seed, tag=False):
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
     return {"agent_steps_per_s": n * K / el, "ms_per_step": 1e3 * el / K, "agents": n,
-            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "latency_kind": "eager env_step calls, HIP events"}
 
 
-def bench_serving(flock, workloads, duration, rate=20.0, lo=500, hi=50000, steps=200, seed=0,
-                  burst=48):
-    """Serving loop: Poisson arrivals of episode requests, one closed-loop step per tick.
+def _serve(flock, pol, arrivals, sizes, boxes, states, steps, max_slots=64, arena=8 << 30):
+    """Replay `arrivals` (seconds) in real time against one server; one tick per loop."""
+    srv = flock.Server(pol, arena, max_slots=max_slots)
+    ids, lat, agents, ticks, max_run, run_sum = [], [], 0, 0, 0, 0
+    i, t0, busy = 0, time.perf_counter(), 0.0
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i] <= now:
+            p = flock.Params(n_agents=int(sizes[i]), box=float(boxes[i]), sectors=V)
+            ids.append(srv.submit(p, states[i], steps)[0])
+            i += 1
+        ts = time.perf_counter()
+        n_run, ag = srv.tick()
+        te = time.perf_counter()
+        if n_run:
+            lat.append(te - ts)
+            busy += te - ts
+            agents += ag
+            ticks += 1
+            run_sum += n_run
+            max_run = max(max_run, n_run)
+        elif i == len(arrivals):
+            if all(srv.poll(r)[0] == srv.FINISHED for r in ids):
+                break
+        else:
+            time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    for r in ids:
+        srv.result(r)
+    return {"requests": len(ids), "ticks": ticks, "max_running": max_run,
+            "mean_running": run_sum / ticks if ticks else 0.0,
+            "p50_ms": 1e3 * percentile(lat, 50) if lat else 0.0,
+            "p99_ms": 1e3 * percentile(lat, 99) if lat else 0.0,
+            "agent_steps_per_s_busy": agents / busy if busy else 0.0,
+            "agent_steps_per_s_wall": agents / wall, "wall_s": wall,
+            "offered_agent_steps_per_s": float(np.sum(sizes)) * steps / max(arrivals[-1], 1e-9)
+            if len(arrivals) else 0.0}
 
-    Phase 1 replays `duration` seconds of Poisson arrivals (rate/s) in real
-    time; phase 2 submits `burst` requests at once (saturation).  Reports the
-    tick (= step) latency percentiles and agent-steps/s while busy.
+
+def bench_serving(flock, workloads, duration=60.0, rates=(20, 100, 500, 2000, 5000), lo=500,
+                  hi=50000, steps=200, seed=0, max_requests=2000, window=4.0):
+    """Serving loop (continuous batching, fused BF16 policy): Poisson arrivals
+    of episode requests, one closed-loop step per tick over every running
+    request; the tick (= step) latency is the host wall time of srv_tick, which
+    ends with a stream synchronisation.
+
+    First `duration` seconds of arrivals at rates[0]/s; then each rate of
+    `rates` for min(window, max_requests / rate) seconds of arrivals, drained,
+    stopping after the first rate whose p99 tick latency exceeds twice its p50.
     """
-    import math
     ws, bs = workloads.xavier_weights([V, 64, 64, 2], seed=0)
     pol = flock.Policy(ws, bs)
 
-    def run(arrivals, sizes, boxes, env_offset):
-        srv = flock.Server(pol, 8 << 30, max_slots=64)
-        states = [workloads.uniform_state(int(n), float(b), seed=seed, env=env_offset + k)
+    def point(rate, dur, seed_k):
+        arrivals = workloads.poisson_arrivals(rate, dur, seed_k)[:max_requests]
+        sizes, boxes = workloads.uneven_env_sizes(len(arrivals), lo, hi, seed=seed_k + 1)
+        states = [workloads.uniform_state(int(n), float(b), seed=seed_k, env=k)
                   for k, (n, b) in enumerate(zip(sizes, boxes))]
-        ids, lat, agents, ticks, max_run = [], [], 0, 0, 0
-        i, t0, busy = 0, time.perf_counter(), 0.0
-        while True:
-            now = time.perf_counter() - t0
-            while i < len(arrivals) and arrivals[i] <= now:
-                p = flock.Params(n_agents=int(sizes[i]), box=float(boxes[i]), sectors=V)
-                ids.append(srv.submit(p, states[i], steps)[0])
-                i += 1
-            ts = time.perf_counter()
-            n_run, ag = srv.tick()
-            te = time.perf_counter()
-            if n_run:
-                lat.append(te - ts)
-                busy += te - ts
-                agents += ag
-                ticks += 1
-                max_run = max(max_run, n_run)
-            elif i == len(arrivals):
-                if all(srv.poll(r)[0] == srv.FINISHED for r in ids):
-                    break
-            else:
-                time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t0))))
-        wall = time.perf_counter() - t0
-        for r in ids:
-            srv.result(r)
-        return {"requests": len(ids), "ticks": ticks, "max_running": max_run,
-                "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
-                "agent_steps_per_s_busy": agents / busy if busy else 0.0,
-                "agent_steps_per_s_wall": agents / wall, "wall_s": wall}
+        res = _serve(flock, pol, arrivals, sizes, boxes, states, steps)
+        res.update({"rate_per_s": rate, "arrival_s": float(dur),
+                    "largest_request": int(np.max(sizes)) if len(sizes) else 0})
+        return res
 
-    arrivals = workloads.poisson_arrivals(rate, duration, seed)
-    sizes, boxes = workloads.uneven_env_sizes(len(arrivals), lo, hi, seed=seed + 1)
-    poisson = run(arrivals, sizes, boxes, 0)
-    bs_sizes, bs_boxes = workloads.uneven_env_sizes(burst, lo, hi, seed=seed + 2)
-    burst_res = run(np.zeros(burst), bs_sizes, bs_boxes, 10000)
-    return {"workload": f"Poisson arrivals {rate}/s for {duration} s, N log-uniform [{lo}, {hi}], "
-                        f"side 4 sqrt(N), {steps} steps each, fused BF16 policy; then a burst of "
-                        f"{burst} requests",
-            "poisson": poisson, "burst": burst_res}
+    log(f"[bench] serving: Poisson {rates[0]}/s for {duration} s")
+    long_run = point(rates[0], duration, seed)
+    sweep = []
+    for k, rate in enumerate(rates):
+        dur = min(window, max_requests / rate)
+        log(f"[bench] serving: rate {rate}/s for {dur:.2f} s")
+        r = point(rate, dur, seed + 100 * (k + 1))
+        sweep.append(r)
+        if r["p99_ms"] > 2.0 * r["p50_ms"]:
+            break
+    return {"workload": f"Poisson arrivals, N log-uniform [{lo}, {hi}], side 4 sqrt(N), 16 "
+                        f"sectors, {steps} steps each, fused BF16 policy, at most 64 running",
+            "poisson": {**long_run, "rate_per_s": rates[0], "arrival_s": duration},
+            "rate_sweep": sweep}
+
+
+def bench_policy(flock, workloads, envs, K, W):
+    """Closed-loop step (env_step_policy) over the 200 x 5,000-agent batch:
+    the policy as its own launch before the step (the default) against the
+    policy run inside the view sweep (policy fusion on).  Eager calls, HIP
+    events over K steps each."""
+    import torch
+    batch = flock.Batch(envs)
+    fused_batch = flock.Batch(envs)
+    fused_batch.set_policy_fusion(True)
+    G = batch.n
+    ws, bs = workloads.xavier_weights([V, 64, 64, 2], seed=0)
+    pol = flock.Policy(ws, bs)
+    obs = torch.empty(G, V, device="cuda")
+    act = torch.zeros(G, 2, device="cuda")
+    rew = torch.empty(G, device="cuda")
+    stream = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    with torch.cuda.stream(stream):
+        batch.step(act, obs, rew, stream)         # a current view
+        for _ in range(W):
+            fused_batch.step_policy(pol, act, obs, rew, stream)
+        ev[0].record(stream)
+        for _ in range(K):
+            fused_batch.step_policy(pol, act, obs, rew, stream)
+        ev[1].record(stream)
+        for _ in range(W):
+            batch.step_policy(pol, act, obs, rew, stream)
+        ev[2].record(stream)
+        for _ in range(K):
+            batch.step_policy(pol, act, obs, rew, stream)
+        ev[3].record(stream)
+        for _ in range(K):
+            pol.forward(obs, act, stream)
+        ev[4].record(stream)
+        stream.synchronize()
+    assert torch.isfinite(obs).all() and torch.isfinite(act).all()
+    fused = ev[0].elapsed_time(ev[1]) / K
+    separate = ev[2].elapsed_time(ev[3]) / K
+    pol_ms = ev[3].elapsed_time(ev[4]) / K
+    flop = 2 * G * (V * 64 + 64 * 64 + 64 * 2)
+    return {"workload": f"{len(envs)} envs x 5,000 agents, closed loop, 16 -> 64 -> 64 -> 2 "
+                        "BF16 policy (MFMA 16x16x32, FP32 accumulate)",
+            "agents": G, "fused_ms_per_step": fused, "separate_ms_per_step": separate,
+            "policy_kernel_ms": pol_ms, "fused_agent_steps_per_s": G / (fused * 1e-3),
+            "separate_agent_steps_per_s": G / (separate * 1e-3),
+            "mlp_flop_per_step": flop,
+            "policy_kernel_mfma_frac": flop / (pol_ms * 1e-3) / 2.5e15}
 
 
 def bench_rollout(flock, workloads, reps=3):
@@ -322,7 +416,7 @@ def bench_graph(flock, workloads, steps=50):
                     "frac": algo / (ms * 1e-3) / HBM_PEAK}}
 
 
-def cpu_baseline(seconds):
+def cpu_baseline_inproc(seconds):
     """The oracle (all-pairs, FP64 view) on the host, 5,000-agent env, bounded sample."""
     import oracle
     import workloads
@@ -340,6 +434,23 @@ def cpu_baseline(seconds):
             "kind": "oracle",
             "sample": f"one 5,000-agent env (side 316, 16 sectors), first {steps} steps "
                       f"(move + all-pairs view/reward), {el:.1f} s"}
+
+
+def cpu_baseline(seconds):
+    """The oracle timed in child processes (before this process touches the
+    GPU): on every host core, then on one."""
+    import subprocess
+    out = {}
+    for label, threads in (("all", None), ("one", 1)):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                            str(seconds)], env=env, capture_output=True, text=True, check=True)
+        out[label] = json.loads(r.stdout.strip().splitlines()[-1])
+    res = dict(out["all"])
+    res["single_thread"] = out["one"]
+    return res
 
 
 def sweep_work(envs, radius=8.0):
@@ -380,9 +491,11 @@ def sweep_work(envs, radius=8.0):
 
 
 def alu_roofline(work, sweep_ms):
+    """The textbook cell list's modelled lane operations over the sweep's time:
+    an upper reference, not a bound (the kernel tests fewer candidates than
+    the textbook 3 x 3 block, so this can exceed the issue peak)."""
     achieved = work["lane_ops"] / (sweep_ms * 1e-3)
-    return {"achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s",
-            "frac": achieved / VALU_PEAK}
+    return {"modelled_T_lane_ops": achieved / 1e12, "issue_peak_T": VALU_PEAK / 1e12}
 
 
 def sweep_source_hash():
@@ -392,8 +505,9 @@ def sweep_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(agents):
-    """HBM bytes per sweep launch from the committed PMC summary, if it is current."""
+def profile_record(agents):
+    """The committed PMC summary of the main leg's sweep (HBM bytes and VALU
+    instructions per launch), if it was taken from the current kernel source."""
     path = os.path.join(ROOT, "profiles", "sweep_flock5k_x200_traffic.json")
     if not os.path.exists(path):
         return None
@@ -401,7 +515,7 @@ def traffic_from_profiles(agents):
         t = json.load(f)
     if t.get("kernel_source_sha") != sweep_source_hash() or t.get("agents") != agents:
         return None
-    return t.get("bytes_per_launch")
+    return t
 
 
 def main():
@@ -413,19 +527,29 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="run the main batched leg only")
-    ap.add_argument("--legs", default="plain,50k,uneven,paper,tag,rollout,graph,serving",
-                    help="comma list of extra legs: plain, 50k, uneven, paper, tag, rollout, "
-                         "graph, serving")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--legs", default="plain,policy,50k,uneven,paper,tag,rollout,graph,serving",
+                    help="comma list of extra legs: plain, policy, 50k, uneven, paper, tag, "
+                         "rollout, graph, serving")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--cpu-baseline-child", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.cpu_baseline_child is not None:
+        print(json.dumps(cpu_baseline_inproc(args.cpu_baseline_child)), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the flock step has no multi-GPU path "
               "(independent envs would shard across GPUs with no communication); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (before the GPU is used)")
+        cpu = cpu_baseline(args.cpu_seconds)
 
     import torch
 
@@ -452,6 +576,9 @@ def main():
     if "plain" in legs:
         log("[bench] plain 5k")
         extra["plain"] = bench_plain(envs[0], 5000, K, W, seed=2)
+    if "policy" in legs:
+        log("[bench] closed loop with the fused policy")
+        extra["policy"] = bench_policy(flock, workloads, envs, min(K, 100), W)
     del envs
     if "50k" in legs:
         for name, init in (("blobs50k", "blobs"), ("uniform50k", "uniform")):
@@ -508,7 +635,7 @@ def main():
                         "field of view 250 degrees, speed appended (129 values)",
             "cell_reach": pf_reach, "sweep_lanes": pf_lanes, "tuned_ms": pf_ms,
             "plain": plain, "batched_x20": bat, "sweep_work_per_launch": work,
-            "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"]),
+            "sweep_valu_lane_ops_model": alu_roofline(work, bat["phase_ms"]["sweep"]),
             "sweep_hbm_frac": pf_bytes * b10.n / (bat["phase_ms"]["sweep"] * 1e-3) / HBM_PEAK}
         del b10, e10
     if "tag" in legs:
@@ -533,7 +660,7 @@ def main():
                         "channels of 64 sectors, field of view 250 degrees, touch distance 1",
             "cell_reach": tg_reach, "sweep_lanes": tg_lanes, "tuned_ms": tg_ms,
             "plain": plain, "batched_x20": bat, "sweep_work_per_launch": work,
-            "sweep_alu": alu_roofline(work, bat["phase_ms"]["sweep"])}
+            "sweep_valu_lane_ops_model": alu_roofline(work, bat["phase_ms"]["sweep"])}
         del b11, e11
     if "rollout" in legs:
         log("[bench] experience collection")
@@ -543,7 +670,7 @@ def main():
         extra["graph"] = bench_graph(flock, workloads)
     if "serving" in legs:
         log("[bench] serving")
-        extra["serving"] = bench_serving(flock, workloads, args.serve_seconds)
+        extra["serving"] = bench_serving(flock, workloads, duration=args.serve_seconds)
 
     if args.copy_calib_mib:
         src = torch.ones(args.copy_calib_mib << 18, device="cuda")
@@ -553,24 +680,36 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # Roofline of the dominant kernel (the neighbour sweep) against HBM: the
+    # step's algorithmic bytes, 44 + 4v per agent-step (read x, y, heading,
+    # speed and the action; write the state, the view and the reward), times
+    # the agents one launch covers, over the launch's average duration (HIP
+    # events on the stream, eager steps).  The sweep is bound by vector issue
+    # in practice; the committed PMC record gives that fraction when current.
     sweep_ms = main_res["phase_ms"]["sweep"]
-    hbm_achieved = SWEEP_BYTES * G / (sweep_ms * 1e-3)
-    traffic = traffic_from_profiles(G)
-    # The sweep is bound by vector-ALU issue (tests and sector binning per
-    # candidate), not by its bytes: the ALU roofline is the binding one.
-    roofline = {"kernel": "k_sweep", "bound": "alu", **alu_roofline(main_work, sweep_ms),
-                "traffic": traffic, "avg_launch_ms": sweep_ms,
-                "work_per_launch": main_work,
-                "ops_model": f"{OPS_PER_CANDIDATE} lane-ops per candidate test + "
-                             f"{OPS_PER_NEIGHBOUR} per neighbour",
-                "hbm": {"algorithmic_bytes_per_launch": SWEEP_BYTES * G,
-                        "achieved_GBps": hbm_achieved / 1e9, "frac": hbm_achieved / HBM_PEAK},
-                "step_hbm_frac": main_res["agent_steps_per_s"] * STEP_BYTES / HBM_PEAK}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline")
-        cpu = cpu_baseline(args.cpu_seconds)
+    algo = STEP_BYTES * G
+    achieved = algo / (sweep_ms * 1e-3)
+    prof = profile_record(G)
+    traffic = prof.get("bytes_per_launch") if prof else None
+    roofline = {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": traffic,
+                "traffic_over_algorithmic": traffic / algo if traffic else None,
+                "avg_launch_ms": sweep_ms, "algorithmic_bytes_per_launch": algo,
+                "bytes_model": f"44 + 4v = {STEP_BYTES} B per agent-step x {G} agents",
+                "step": {"achieved": STEP_BYTES * main_res["agent_steps_per_s"] / 1e9,
+                         "frac": STEP_BYTES * main_res["agent_steps_per_s"] / HBM_PEAK},
+                "valu_issue_frac": (prof["valu_insts_per_launch"] / (VALU_ISSUE_PEAK *
+                                                                      sweep_ms * 1e-3))
+                if prof and prof.get("valu_insts_per_launch") else None,
+                "textbook_work": main_work}
+    for name in ("blobs50k", "uniform50k"):
+        if name in extra:
+            b = extra[name]["batched_x20"]
+            b["step_hbm_frac"] = STEP_BYTES * b["agent_steps_per_s"] / HBM_PEAK
+            extra[name]["plain"]["step_hbm_frac"] = (STEP_BYTES *
+                                                      extra[name]["plain"]["agent_steps_per_s"] /
+                                                      HBM_PEAK)
 
     out = {
         "metric": "agent-steps/s batched vs plain at 5k/50k agents; p50/p99 step latency",

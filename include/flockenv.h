@@ -232,6 +232,21 @@ int env_batch_set_sweep_lanes(env_batch_t *b, int lanes);
 /* *lanes receives the lanes per agent the batched sweep uses now. */
 int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes);
 
+/* Policy fusion for env_step_policy and env_rollout (Sec. 4.3: one policy
+ * shared by all agents acting on their own views), off by default.  When on,
+ * and the batch's sweep uses one or four lanes per agent, the policy runs
+ * inside the step's view sweep on the views it has just produced (still in
+ * LDS), so no separate policy launch reads them back: env_rollout evaluates
+ * only its first action separately; env_step_policy keeps the next step's
+ * actions in the batch workspace and applies them on the next call with the
+ * same pol and obs pointer when no env of the batch changed in between (any
+ * other stepping call, env_set_state or env_reset), so obs must not be
+ * written between such calls.  Results are bitwise the same either way.  Off
+ * by default because on MI355X the fused step is slower: the network's tanh
+ * work is vector-ALU bound and its registers and LDS lower the occupancy of
+ * the issue-bound sweep.  ENV_EINVAL for a NULL batch. */
+int env_batch_set_policy_fusion(env_batch_t *b, int on);
+
 /* off[n_envs + 1] (host) receives the row offsets described above. */
 int env_batch_offsets(const env_batch_t *b, int64_t *off);
 
@@ -317,9 +332,9 @@ int pol_sample(pol_t *pol, const float *obs, int64_t n, const float *log_std, co
  * launches of all steps are captured once into a HIP graph and replayed
  * (re-captured when an argument changes); `stream` must not be the null
  * stream.  Results equal `steps` rounds of pol_sample (or pol_forward) and
- * env_step_batched, bitwise.  For flock batches only the first action comes
- * from a separate policy evaluation: each step's view sweep evaluates (and
- * samples) the next step's action from the views it has just produced. */
+ * env_step_batched, bitwise (also with env_batch_set_policy_fusion on, when
+ * only the first action comes from a separate policy evaluation and each
+ * step's view sweep evaluates and samples the next one). */
 int env_rollout(env_batch_t *b, pol_t *pol, int steps, const float *log_std, const float *eps,
                 float *obs, float *act, float *logp, float *reward, void *stream);
 
@@ -350,14 +365,9 @@ int rl_gae(int steps, int64_t n, float gamma, float lambda, const float *reward,
  * batched step with those actions.  obs (device [G][d]) is read as the
  * current view and overwritten by the new one; act (device [G][2]) receives
  * the actions taken; reward (device [G]).
- * The policy runs inside the step's view sweep on the views it has just
- * produced, still on chip, and the next step's actions are kept in the batch
- * workspace: a following env_step_policy call with the same pol and obs
- * pointer, with no env of the batch changed in between (by any other stepping
- * call, env_set_state or env_reset), applies them without evaluating the
- * policy again, so obs must not be written between such calls.  Otherwise
- * (the first call, or after a change) the policy is evaluated on obs first.
- * The actions are bitwise those of pol_forward on the same views. */
+ * The actions are bitwise those of pol_forward on the same views.  With
+ * env_batch_set_policy_fusion on (and a sweep of one or four lanes per
+ * agent), see there. */
 int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *reward,
                     void *stream);
 

@@ -276,6 +276,7 @@ struct flock_batch {
     hipEvent_t events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     // env_step_policy's next actions, computed inside its view sweep: valid
     // for the next call with the same policy and obs while no env changed.
+    bool fuse_policy = false;        // env_batch_set_policy_fusion
     float2 *act_next = nullptr;      // [G] in the workspace
     bool next_valid = false;
     const void *next_pol = nullptr;
@@ -358,21 +359,6 @@ int env_load_host_state(env_t *env, const float *x, const float *y, const float 
         e = launch_load_state(stage, stage + n, stage + 2 * (size_t)n, stage + 3 * (size_t)n,
                               env->lay.rec[env->parity], env->lay.id[env->parity], n, s);
     if (e != hipSuccess) return hip_fail(e, "state upload");
-    return ENV_OK;
-}
-
-int env_reset_policy(env_t *env, float *obs, const PolFuse &pf, hipStream_t s) {
-    if (!env->has_state) return set_error(ENV_ESTATE, "reset before the state is loaded");
-    const int n = env->p.n_agents;
-    int rc = upload_own(env, s);
-    if (rc != ENV_OK) return rc;
-    hipError_t e = launch_zero_f64(env->lay.ret[env->parity], n, s);
-    if (e == hipSuccess) e = launch_step(env->plan, env->parity, 0, nullptr, obs, nullptr, 0, s,
-                                         nullptr, &pf);
-    if (e != hipSuccess) return hip_fail(e, "reset with the policy");
-    if (n > 0) env->parity ^= 1;
-    env->reset_done = true;
-    ++env->gen;
     return ENV_OK;
 }
 
@@ -779,6 +765,17 @@ int env_batch_set_sweep_lanes(env_batch_t *b, int lanes) {
     return ENV_OK;
 }
 
+int env_batch_set_policy_fusion(env_batch_t *b, int on) {
+    if (!b) return fail(ENV_EINVAL, "batch is NULL");
+    const bool want = on != 0;
+    if (want != b->fuse_policy) {
+        drop_graphs(b);
+        b->fuse_policy = want;
+        b->next_valid = false;
+    }
+    return ENV_OK;
+}
+
 int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes) {
     if (!b || !lanes) return fail(ENV_EINVAL, "NULL argument");
     *lanes = b->plan.lanes;
@@ -968,6 +965,7 @@ static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, co
                                  key_of(obs), key_of(act), key_of(logp), key_of(reward),
                                  key_of(s), ((uint64_t)lsb[0] << 32) | lsb[1],
                                  ((uint64_t)lsb[2] << 32) | lsb[3]};
+    const bool fuse_plan = !tag && b->fuse_policy && plan_fuses_policy(b->plan);
     rc = capture_graph(b->rgc[t], std::move(key), s, [&]() {
         hipError_t le = hipSuccess;
         for (int k = 0; k < steps && le == hipSuccess; ++k) {
@@ -980,13 +978,14 @@ static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, co
                 le = policy_launch_typed(pol, b->plan, tk, 0, o_k, e_k, ls, a_k, l_k, s);
                 if (le == hipSuccess)
                     le = policy_launch_typed(chaser, b->plan, tk, 1, o_k, e_k, ls + 2, a_k, l_k, s);
-            } else if (k == 0) {
-                // the first action; each step's view sweep then computes the next
+            } else if (k == 0 || !fuse_plan) {
+                // the first action; when the plan fuses, each step's view
+                // sweep then computes the next
                 le = eps ? policy_launch_sample(pol, o_k, G, e_k, ls, a_k, l_k, s)
                          : policy_launch(pol, o_k, G, a_k, s);
             }
             PolFuse pf{};
-            const bool fuse = !tag && k + 1 < steps;
+            const bool fuse = fuse_plan && k + 1 < steps;
             if (fuse) {
                 pf = policy_fuse_args(pol);
                 pf.act = reinterpret_cast<float2 *>(act + (size_t)(k + 1) * G * 2);
@@ -1055,12 +1054,20 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
         return fail(ENV_EINVAL, "policy input %d != observation length %d", policy_in_dim(pol),
                     b->plan.obs_dim);
     hipStream_t s = as_stream(stream);
-    bool have_next = b->next_valid && b->next_pol == policy_weights(pol) && b->next_obs == obs;
-    for (size_t k = 0; k < b->envs.size() && have_next; ++k)
-        have_next = b->envs[k]->gen == b->next_gen[k];
     int t;
     int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
+    if (!b->fuse_policy || !plan_fuses_policy(b->plan)) {
+        // the policy as its own launch before the step
+        hipError_t e = policy_launch(pol, obs, b->plan.G, act, s);
+        if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
+        if (e != hipSuccess) return hip_fail(e, "env_step_policy");
+        batch_advance(b, 1);
+        return ENV_OK;
+    }
+    bool have_next = b->next_valid && b->next_pol == policy_weights(pol) && b->next_obs == obs;
+    for (size_t k = 0; k < b->envs.size() && have_next; ++k)
+        have_next = b->envs[k]->gen == b->next_gen[k];
     float *nxt = reinterpret_cast<float *>(b->act_next);
     hipError_t e = hipSuccess;
     if (!have_next) e = policy_launch(pol, obs, b->plan.G, nxt, s);

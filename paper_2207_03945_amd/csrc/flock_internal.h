@@ -145,7 +145,12 @@ hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1
 // act/obs/reward are batch-wide arrays ([G][2], [G][v], [G]); when NULL the
 // kernels use each env's own act/obs/rew rows from its descriptor.
 // add_return = 1 adds the reward to the FP64 returns.
-// pf (not null): the policy runs in the sweep (see PolFuse); tag plans excluded.
+// Whether a step of this plan can run the policy in its view sweep (PolFuse):
+// flock plans whose sweep uses one or four lanes per agent (blocks of 256 or
+// 64 agents, over which the network's weights are staged once).
+bool plan_fuses_policy(const StepPlan &p);
+// pf (not null): the policy runs in the sweep (see PolFuse); only for plans
+// with plan_fuses_policy (hipErrorInvalidValue otherwise).
 // act_copy (not null, batch rows [G][2]): the move also writes each applied
 // action (as read, before its clamp) there.
 hipError_t launch_step(const StepPlan &p, int table, int do_move, const float *act, float *obs,
@@ -194,8 +199,6 @@ void env_advance(env_t *env, int steps);        // record `steps` stepped elsewh
 // Copy a host state into the env (async on s; host arrays must outlive the copy).
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s);
-// env_reset whose view sweep also runs the policy (pf) on the initial view.
-int env_reset_policy(env_t *env, float *obs, const PolFuse &pf, hipStream_t s);
 // Device FP64 returns of the env in agent order, into `out` (device [n]).
 int env_returns_to(env_t *env, double *out, hipStream_t s);
 // Bytes of the batch sort scratch for G agents, C cells, E envs.

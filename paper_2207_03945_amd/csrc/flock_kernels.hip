@@ -881,15 +881,27 @@ static_assert(kFlatUnroll <= kSortPad + 1 && kUnrollMax * 64 <= kSortPad + 1,
 // block's agents are cut into 16-agent tiles spread over its waves, and each
 // tile goes through mlp_tile as in the policy kernels.  LDS after the minima:
 // the network constants, per-agent speed / env / id, one hidden tile per wave.
+// With one lane per agent a wave's agents are its own lanes: each wave runs
+// its tiles as soon as its views are written, reading the inputs of its four
+// tiles into registers first when they fit one chunk (kc == 1), after which
+// its own stretch of the minima (16 rows of 64 words, v >= 16) serves as its
+// hidden tile; otherwise (and with four lanes per agent, which needs a block
+// barrier) the hidden tiles have a region of their own.  Smaller blocks (lane
+// groups of 16 or 64) would read the weights once per tile and are not fused.
 struct SweepPolLds {
     int pc, speed, env, id, hid, words;  // offsets in 32-bit words from the minima's start
 };
-__host__ __device__ constexpr SweepPolLds sweep_pol_lds(int min_words, int A, int NT) {
+__host__ __device__ constexpr bool sweep_pol_alias(int G, int kc, int vs) {
+    return G == 1 && kc == 1 && vs >= 16;
+}
+__host__ __device__ constexpr SweepPolLds sweep_pol_lds(int min_words, int A, int NT, int G,
+                                                        bool alias) {
     const int pc = (min_words + 3) & ~3;
     const int speed = pc + (int)((sizeof(PolConsts) + 15) / 16) * 4;
-    const int env = speed + A, id = env + A;
-    const int hid = (id + A + 3) & ~3;
-    return SweepPolLds{pc, speed, env, id, hid, hid + (NT / 64) * 16 * kHidLd / 2};
+    const int per_agent = G == 1 ? 0 : A;  // one lane per agent: shuffled from the owner lane
+    const int env = speed + per_agent, id = env + per_agent;
+    const int hid = (id + per_agent + 3) & ~3;
+    return SweepPolLds{pc, speed, env, id, hid, hid + (alias ? 0 : (NT / 64) * 16 * kHidLd / 2)};
 }
 
 template <int NT, int G, bool kFov, bool kTag, int kM, int kPol = 0>
@@ -908,7 +920,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     uint32_t *smin = s_min + slot;
     if constexpr (G > 1)
         for (int k = li; k < vs; k += G) smin[k * A] = kInfBits;
-    const SweepPolLds PL = sweep_pol_lds(vs * A, A, NT);
+    static_assert(kPol == 0 || G <= 4, "the fused policy needs blocks of at least 64 agents");
+    const SweepPolLds PL = sweep_pol_lds(vs * A, A, NT, G, sweep_pol_alias(G, pf.kc, vs));
     PolConsts *s_pc = reinterpret_cast<PolConsts *>(s_min + PL.pc);
     float *s_speed = reinterpret_cast<float *>(s_min + PL.speed);
     int *s_pe = reinterpret_cast<int *>(s_min + PL.env);
@@ -927,7 +940,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     const DevEnv &E = envs[e];
     const int j = pos - E.agent_base;
     float4 me = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    int nb = 0, col = 0, ti = 0;
+    int nb = 0, col = 0, ti = 0, my_id = 0;
     if (active) {
         me = load_as<(G > 1)>(E.rec_nxt, j);
         const float2 cs = heading_cs(me.z);
@@ -1081,6 +1094,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     };
     if (active) {
         const int id = load_as<kGl>(E.id_nxt, j);
+        my_id = id;
         const float inv_r = E.inv_radius;
         float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
         if (li == 0 && obs_dim > vs) store_as<kGl>(orow, vs, me.w);  // speed after the move (Sec. 4.1)
@@ -1106,20 +1120,98 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                 store_as<kGl>(E.nb, id, nb);
                 store_as<kGl>(E.col, id, col);
             }
-            if constexpr (kPol != 0) {
+            if constexpr (kPol != 0 && G > 1) {
                 s_speed[slot] = me.w;
                 s_pe[slot] = e;
                 s_pid[slot] = id;
             }
         }
-    } else if constexpr (kPol != 0) {
+    } else if constexpr (kPol != 0 && G > 1) {
         if (li == 0) s_pe[slot] = -1;
+    }
+    // The policy's action of a tile's agent from its output pre-activations
+    // (lanes g == 0 of a valid column write).
+    auto write_act = [&](float2 z, int pe, int idj, bool wr) {
+        if (!wr) return;
+        const DevEnv &Ej = envs[pe];
+        const int64_t row = (int64_t)Ej.agent_base + idj;
+        const float2 ev = kPol == 2 ? pf.eps[row] : make_float2(0.0f, 0.0f);
+        const float2 av = pol_output<kPol == 2>(z, pf.max_turn, pf.max_dspeed, ev, pf.sig0, pf.sig1,
+                                                pf.logp_c,
+                                                (kPol == 2 && pf.logp) ? pf.logp + row : nullptr);
+        if (pf.act) pf.act[row] = av;
+        else reinterpret_cast<float2 *>(Ej.act)[idj] = av;
+    };
+    // weight fragments read at use from global memory (cached): held in
+    // registers they would lower the whole kernel's occupancy, staged in LDS
+    // they made the policy phase LDS-bound (measured slower)
+    const int lane = tid & 63, g = lane >> 4, colx = lane & 15;
+    auto w1a = [&](int c, int t) { return pf.P.w1[(c * 4 + t) * 64 + lane]; };
+    auto w2a = [&](int c, int t) { return pf.P.w2[(c * 4 + t) * 64 + lane]; };
+    auto w3a = [&](int c) { return pf.P.w3[c * 64 + lane]; };
+    if constexpr (kPol != 0 && G == 1) {
+        const int w0 = tid - lane;  // the wave's first slot
+        const int my_e = active ? e : -1;
+        const float my_sp = me.w;
+        wave_lds_fence();           // the wave's views in LDS before its reads
+        // inputs of tile t (agents w0 + 16 t + col, owned by lane 16 t + col):
+        // the view, then the speed when the row carries it, zero beyond
+        auto input = [&](int t, int k, int pe, float sp) {
+            float o = 0.0f;
+            if (pe >= 0) {
+                if (k < vs) o = __uint_as_float(s_min[k * A + w0 + 16 * t + colx]);
+                else if (k == vs && obs_dim > vs) o = sp;
+            }
+            return (__bf16)o;
+        };
+        if (sweep_pol_alias(G, pf.kc, vs)) {
+            bf16x8 xr[4];
+            int te[4], ti4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int src = 16 * t + colx;
+                te[t] = __shfl(my_e, src, 64);
+                ti4[t] = __shfl(my_id, src, 64);
+                const float sp = __shfl(my_sp, src, 64);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) xr[t][jj] = input(t, 8 * g + jj, te[t], sp);
+            }
+            wave_lds_fence();  // every lane's reads before the stretch becomes the hidden tile
+            // row r: minima row r of the wave's stretch, skewed by (r % 8) * 4 words
+            auto hrow = [&](int r) {
+                return reinterpret_cast<__bf16 *>(s_min + r * A + w0 + (r & 7) * 4);
+            };
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float2 z =
+                    mlp_tile(1, [&](int) { return xr[t]; }, w1a, w2a, w3a, *s_pc, hrow, lane);
+                write_act(z, te[t], ti4[t], g == 0 && te[t] >= 0);
+            }
+        } else {
+            __bf16 *s_hid = reinterpret_cast<__bf16 *>(s_min + PL.hid) + (size_t)(tid >> 6) * 16 * kHidLd;
+            auto hrow = [&](int r) { return s_hid + r * kHidLd; };
+            for (int t = 0; t < 4; ++t) {
+                const int src = 16 * t + colx;
+                const int pe = __shfl(my_e, src, 64), idj = __shfl(my_id, src, 64);
+                const float sp = __shfl(my_sp, src, 64);
+                auto xb = [&](int c) {
+                    bf16x8 x;
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) x[jj] = input(t, 32 * c + 8 * g + jj, pe, sp);
+                    return x;
+                };
+                const float2 z = mlp_tile(pf.kc, xb, w1a, w2a, w3a, *s_pc, hrow, lane);
+                write_act(z, pe, idj, g == 0 && pe >= 0);
+            }
+        }
+        return;
     }
     if constexpr (kPol != 0) {
         __syncthreads();  // every agent's view, speed and row are in LDS
         constexpr int kTiles = (A + 15) / 16;
-        const int wid = tid >> 6, lane = tid & 63, g = lane >> 4, colx = lane & 15;
+        const int wid = tid >> 6;
         __bf16 *s_hid = reinterpret_cast<__bf16 *>(s_min + PL.hid) + (size_t)wid * 16 * kHidLd;
+        auto hrow = [&](int r) { return s_hid + r * kHidLd; };
         if (wid >= kTiles) return;
         for (int tile = wid; tile < kTiles; tile += NT / 64) {
             const int sl = tile * 16 + colx;
@@ -1141,23 +1233,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                 }
                 return x;
             };
-            // weights read at use (they stay in the vector L1 cache): held in
-            // registers they would lower the whole kernel's occupancy
-            auto w1a = [&](int c, int t) { return pf.P.w1[(c * 4 + t) * 64 + lane]; };
-            auto w2a = [&](int c, int t) { return pf.P.w2[(c * 4 + t) * 64 + lane]; };
-            const float2 z = mlp_tile(pf.kc, xb, w1a, w2a, *s_pc, s_hid, lane);
-            if (g == 0 && valid) {
-                const DevEnv &Ej = envs[pe];
-                const int idj = s_pid[sl];
-                const int64_t row = (int64_t)Ej.agent_base + idj;
-                const float2 ev = kPol == 2 ? pf.eps[row] : make_float2(0.0f, 0.0f);
-                const float2 av =
-                    pol_output<kPol == 2>(z, *s_pc, pf.max_turn, pf.max_dspeed, ev, pf.sig0,
-                                          pf.sig1, pf.logp_c,
-                                          (kPol == 2 && pf.logp) ? pf.logp + row : nullptr);
-                if (pf.act) pf.act[row] = av;
-                else reinterpret_cast<float2 *>(Ej.act)[idj] = av;
-            }
+            const float2 z = mlp_tile(pf.kc, xb, w1a, w2a, w3a, *s_pc, hrow, lane);
+            write_act(z, pe, valid ? s_pid[sl] : 0, g == 0 && valid);
         }
     }
 }
@@ -1262,6 +1339,8 @@ hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1
     return hipGetLastError();
 }
 
+bool plan_fuses_policy(const StepPlan &p) { return !p.tag && (p.lanes == 1 || p.lanes == 4); }
+
 hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     const int64_t n = p.C > 0 ? p.C : 1;
     hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C);
@@ -1273,9 +1352,11 @@ template <int NT, int G, bool kFov, bool kTag, int kM = 0, int kPol = 0>
 void launch_sweep_v(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, float *reward,
                     int add_return, hipStream_t s, const PolFuse *pf) {
     constexpr int A = NT / G;
-    const int min_words = (kTag ? 2 : 1) * p.v * A;
-    const size_t lds = (size_t)(kPol ? sweep_pol_lds(min_words, A, NT).words : min_words) *
-                       sizeof(uint32_t);
+    const int vs = (kTag ? 2 : 1) * p.v, min_words = vs * A;
+    const size_t lds =
+        (size_t)(kPol ? sweep_pol_lds(min_words, A, NT, G, sweep_pol_alias(G, pf->kc, vs)).words
+                      : min_words) *
+        sizeof(uint32_t);
     hipLaunchKernelGGL((k_sweep<NT, G, kFov, kTag, kM, kPol>), dim3(blocks_for(Gtot, A)), dim3(NT),
                        lds, s, p.a, envs, p.n_envs, Gtot, p.v, p.obs_dim, obs, reward, add_return,
                        pf ? *pf : PolFuse{});
@@ -1301,10 +1382,9 @@ void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, f
         else launch_sweep_v<NT, G, false, true>(p, envs, Gtot, obs, reward, add_return, s, nullptr);
     } else if (!pf) {
         launch_sweep_flock<NT, G, 0>(p, envs, Gtot, obs, reward, add_return, s, nullptr);
-    } else if (pf->mode == 2) {
-        launch_sweep_flock<NT, G, 2>(p, envs, Gtot, obs, reward, add_return, s, pf);
-    } else {
-        launch_sweep_flock<NT, G, 1>(p, envs, Gtot, obs, reward, add_return, s, pf);
+    } else if constexpr (G <= 4) {
+        if (pf->mode == 2) launch_sweep_flock<NT, G, 2>(p, envs, Gtot, obs, reward, add_return, s, pf);
+        else launch_sweep_flock<NT, G, 1>(p, envs, Gtot, obs, reward, add_return, s, pf);
     }
 }
 }  // namespace
@@ -1312,7 +1392,7 @@ void launch_sweep(const StepPlan &p, const DevEnv *envs, int Gtot, float *obs, f
 hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_move,
                         const float *act, float *obs, float *reward, int add_return,
                         hipStream_t s, const PolFuse *pf, float *act_copy) {
-    if (pf && p.tag) return hipErrorInvalidValue;  // the fused policy serves flock plans
+    if (pf && !plan_fuses_policy(p)) return hipErrorInvalidValue;
     if (p.G == 0) return hipSuccess;
     const int G = (int)p.G, C = (int)p.C;
     const DevEnv *envs = p.a.envs[table & 1];

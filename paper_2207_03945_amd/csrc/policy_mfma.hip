@@ -36,10 +36,10 @@ PolLayout carve_pol(char *base, int kc) {
     Carver cv{base, 0};
     l.w1 = cv.take<bf16x8>((size_t)kc * 4 * 64);
     l.w2 = cv.take<bf16x8>(2 * 4 * 64);
+    l.w3 = cv.take<bf16x8>(2 * 64);
     l.b1 = cv.take<float>(64);
     l.b2 = cv.take<float>(64);
-    l.w3 = cv.take<float>(128);
-    l.b3 = cv.take<float>(2);
+    l.b3 = cv.take<float>(4);
     l.bytes = align_up(cv.off, 256);
     return l;
 }
@@ -118,11 +118,13 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
     if (!kLdsW1)
 #pragma unroll
         for (int t = 0; t < 4; ++t) w1[t] = P.w1[t * 64 + lane];  // kc == 1
-    bf16x8 w2[2][4];
+    bf16x8 w2[2][4], w3[2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) w2[c][t] = P.w2[(c * 4 + t) * 64 + lane];
+        w3[c] = P.w3[c * 64 + lane];
+    }
 
     const int64_t waves = (int64_t)gridDim.x * (kPolBlock / 64);
     const int64_t tiles = (n + 15) / 16;
@@ -144,11 +146,11 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
             const int rows = n - row0 < 16 ? (int)(n - row0) : 16;
             const float *src = obs + row0 * in_dim;
             const int cnt = rows * in_dim, cnt4 = cnt >> 2;
-            __threadfence_block();  // the previous tile's reads come first
+            wave_lds_fence();  // the previous tile's reads come first
             // zero the tile (columns past in_dim must read as 0)
             uint4 *z = reinterpret_cast<uint4 *>(s_obs);
             for (int i = lane; i < 2 * ld; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
-            __threadfence_block();
+            wave_lds_fence();
             int rb = (4 * lane) / in_dim, kb = 4 * lane - rb * in_dim;
             const int dq = 256 / in_dim, dr = 256 - dq * in_dim;
             const float4 *src4 = reinterpret_cast<const float4 *>(src);
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
                 const int r = e / in_dim;
                 s_obs[r * ld + (e - r * in_dim)] = (__bf16)src[e];
             }
-            __threadfence_block();  // this wave's copies before its reads
+            wave_lds_fence();  // this wave's copies before its reads
         }
         if (envs && valid) {
             const DevEnv &E = envs[env_of_row(base, n_envs, agent)];
@@ -214,13 +216,15 @@ __global__ __launch_bounds__(kPolBlock) void k_policy(PolLayout P, int in_dim, i
         };
         auto w1a = [&](int c, int t) { return kLdsW1 ? s_w1[(c * 4 + t) * 64 + lane] : w1[t]; };
         auto w2a = [&](int c, int t) { return w2[c][t]; };
-        const float2 z = mlp_tile(kc, xb, w1a, w2a, s_pc, s_hid, lane);
+        auto w3a = [&](int c) { return w3[c]; };
+        auto hrow = [&](int r) { return s_hid + r * kHidLd; };
+        const float2 z = mlp_tile(kc, xb, w1a, w2a, w3a, s_pc, hrow, lane);
         if (g == 0 && valid) {
             if constexpr (kOut == kValue) {
-                oa.val[agent] = z.x + s_pc.b3[0];
+                oa.val[agent] = z.x;
             } else {
                 const float2 e = kOut == kSample ? oa.eps[agent] : make_float2(0.0f, 0.0f);
-                *arow = pol_output<kOut == kSample>(z, s_pc, max_turn, max_dspeed, e, oa.sig0,
+                *arow = pol_output<kOut == kSample>(z, max_turn, max_dspeed, e, oa.sig0,
                                                    oa.sig1, oa.logp_c,
                                                    oa.logp ? oa.logp + agent : nullptr);
             }
@@ -423,8 +427,7 @@ int create_net(const float *w, int in_dim, int hidden, int n_out, float max_turn
     const float *W3 = b2 + H;
     const float *b3 = W3 + H * n_out;
     float *b3d = reinterpret_cast<float *>(at(off.b3));
-    b3d[0] = b3[0];
-    b3d[1] = n_out > 1 ? b3[1] : 0.0f;
+    for (int o = 0; o < 4; ++o) b3d[o] = o < n_out ? b3[o] : 0.0f;
     // A operands in lane order: lane (g, col) of chunk c, tile t holds
     // W[32 c + 8 g + j][16 t + col] in element j (zero beyond in_dim)
     uint16_t *w1p = reinterpret_cast<uint16_t *>(at(off.w1));
@@ -444,13 +447,19 @@ int create_net(const float *w, int in_dim, int hidden, int n_out, float max_turn
                     const int k = 32 * c + 8 * (lane / 16) + j, m = 16 * t + lane % 16;
                     w2p[((c * 4 + t) * 64 + lane) * 8 + j] = bf16_bits_rne(W2[k * H + m]);
                 }
+    // output layer: A[m][k] = W3[k][m] for the n_out real rows m, zero rows after
+    uint16_t *w3p = reinterpret_cast<uint16_t *>(at(off.w3));
+    for (int c = 0; c < 2; ++c)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * c + 8 * (lane / 16) + j, m = lane % 16;
+                w3p[(c * 64 + lane) * 8 + j] = bf16_bits_rne(m < n_out ? W3[k * n_out + m] : 0.0f);
+            }
     float *b1d = reinterpret_cast<float *>(at(off.b1));
     float *b2d = reinterpret_cast<float *>(at(off.b2));
-    float *w3d = reinterpret_cast<float *>(at(off.w3));
     for (int h = 0; h < H; ++h) {
         b1d[h] = b1[h];
         b2d[h] = b2[h];
-        for (int o = 0; o < 2; ++o) w3d[o * H + h] = o < n_out ? bf16_round(W3[h * n_out + o]) : 0.0f;
     }
     hipError_t e = hipMemcpyAsync(ws, hb, need, hipMemcpyHostToDevice,
                                   reinterpret_cast<hipStream_t>(stream));

@@ -6,17 +6,19 @@
 // axis is the agent axis; Sec. 5: two hidden layers of 64 units.  Network:
 // in -> 64 -> 64 -> 2, tanh after every layer.
 //
-// Precision: inputs and weights rounded once to BF16 (round to nearest even),
-// products accumulated in FP32 by v_mfma_f32_16x16x32_bf16, biases and the
-// 64 -> 2 output layer in FP32 on the vector ALUs (with BF16-rounded weights).
+// Precision: inputs, weights and both hidden layers' activations rounded once
+// to BF16 (round to nearest even), products accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16 starting from the FP32 biases; tanh evaluated in
+// FP32 as 1 - 2 / (exp(2x) + 1) (absolute error about 1e-7).
 //
-// Layout.  A wave computes the transposed products H1^T = W1^T X^T and
-// H2^T = W2^T H1^T (hidden units as MFMA rows, agents as columns).  Lane
-// l = 16 g + col holds agent col; in register r of output tile t (hidden units
-// 16 t .. 16 t + 15) it holds unit 16 t + 4 g + r, and as a B operand it
-// supplies the eight K values 32 c + 8 g .. + 7 of chunk c.  Layer 1's
-// results reach layer 2 through a per-wave LDS tile of BF16 hidden rows; the
-// weights are packed into A-operand lane order once on the host.
+// Layout.  A wave computes the transposed products H1^T = W1^T X^T,
+// H2^T = W2^T H1^T and Z^T = W3^T H2^T (units as MFMA rows, agents as
+// columns).  Lane l = 16 g + col holds agent col; in register r of output
+// tile t (units 16 t .. 16 t + 15) it holds unit 16 t + 4 g + r, and as a B
+// operand it supplies the eight K values 32 c + 8 g .. + 7 of chunk c.  Each
+// layer's activations reach the next layer's B operand through a per-wave
+// LDS tile of BF16 rows; the weights are packed into A-operand lane order
+// once on the host (the output layer's two rows padded to 16 with zeros).
 //
 // Every caller evaluates a tile through mlp_tile and pol_output, so the same
 // inputs give bitwise the same actions wherever the network runs.
@@ -39,16 +41,16 @@ struct PolLayout {
     // A operands, lane (g = l / 16, col = l % 16), element j of chunk c, tile t:
     bf16x8 *w1;  // [kc][4 tiles][64 lanes]  W1[32 c + 8 g + j][16 t + col] (0 beyond in_dim)
     bf16x8 *w2;  // [2][4 tiles][64 lanes]   W2[32 c + 8 g + j][16 t + col]
+    bf16x8 *w3;  // [2][64 lanes]            W3[32 c + 8 g + j][col] (0 for col >= outputs)
     float *b1;   // [64] by hidden unit
     float *b2;   // [64]
-    float *w3;   // [2 outputs][64] (BF16-rounded)
-    float *b3;   // [2]
+    float *b3;   // [4]: the outputs' biases, zero-padded
     size_t bytes;
 };
 
-// Network constants a block keeps in LDS.
-struct PolConsts {
-    float b1[64], b2[64], w3[128], b3[2];
+// Network biases a block keeps in LDS.
+struct alignas(16) PolConsts {
+    float b1[64], b2[64], b3[4];
 };
 
 __device__ __forceinline__ void load_pol_consts(const PolLayout &P, PolConsts *c, int tid,
@@ -57,79 +59,93 @@ __device__ __forceinline__ void load_pol_consts(const PolLayout &P, PolConsts *c
         c->b1[i] = P.b1[i];
         c->b2[i] = P.b2[i];
     }
-    for (int i = tid; i < 128; i += nthreads) c->w3[i] = P.w3[i];
-    if (tid < 2) c->b3[tid] = P.b3[tid];
+    if (tid < 4) c->b3[tid] = P.b3[tid];
 }
 
+// tanh(x) = 1 - 2 / (exp(2x) + 1): exact limits +-1 when exp overflows or
+// underflows, absolute error about 1e-7 (the subtraction from 1).
 __device__ __forceinline__ float tanh_fast(float x) {
-    x = fminf(fmaxf(x, -15.0f), 15.0f);
     const float e = __expf(2.0f * x);
-    return __fdividef(e - 1.0f, e + 1.0f);
+    return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
-// One tile of 16 agents through the two hidden layers and the output layer's
-// products.  xb(c): this lane's B operand of input chunk c (eight BF16 inputs
-// 32 c + 8 g .. + 7 of agent col, zero beyond the input length); w1(c, t) and
-// w2(c, t): the layer-1 and layer-2 A operands of chunk c, tile t; s_hid: the
-// wave's [16][kHidLd] BF16 hidden tile.  Returns the two output
-// pre-activations without bias (z0, z1), summed over the lane groups, in
-// every lane.
-template <class XB, class W1, class W2>
-__device__ __forceinline__ float2 mlp_tile(int kc, XB xb, W1 w1, W2 w2, const PolConsts &pc,
-                                          __bf16 *s_hid, int lane) {
-    const int g = lane >> 4, col = lane & 15;
-    f32x4 acc1[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
-    for (int c = 0; c < kc; ++c) {
-        const bf16x8 x = xb(c);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1(c, t), x, acc1[t], 0, 0, 0);
-    }
-    // bias + tanh, into the hidden tile as B operand rows of layer 2
-    __threadfence_block();  // the previous tile's reads of the hidden tile come first
+// Bias of accumulator register r of output tile t (units 16 t + 4 g + r).
+__device__ __forceinline__ f32x4 bias4(const float *b, int t, int g) {
+    return *reinterpret_cast<const f32x4 *>(b + 16 * t + 4 * g);
+}
+
+// Orders a wave's own LDS accesses (lanes of one wave write, then read, a
+// tile only that wave uses): a wave's LDS operations complete in issue order,
+// so this only keeps the compiler from moving accesses across it (a
+// workgroup-scope fence would also wait for the wave's outstanding global
+// stores).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// tanh of a tile's accumulators, rounded to BF16 into the wave's hidden tile
+// as B operand rows of the next layer.
+template <class HR>
+__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[4], HR hrow, int g, int col) {
+    wave_lds_fence();  // earlier reads of the hidden tile come first
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         __bf16 hv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hv[r] = (__bf16)tanh_fast(acc1[t][r] + pc.b1[16 * t + 4 * g + r]);
+        for (int r = 0; r < 4; ++r) hv[r] = (__bf16)tanh_fast(acc[t][r]);
         uint2 packed;
         memcpy(&packed, hv, sizeof(packed));
-        *reinterpret_cast<uint2 *>(s_hid + col * kHidLd + 16 * t + 4 * g) = packed;
+        *reinterpret_cast<uint2 *>(hrow(col) + 16 * t + 4 * g) = packed;
     }
-    __threadfence_block();  // the wave's hidden tile before its reads
-    f32x4 acc2[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
+    wave_lds_fence();  // the wave's hidden tile before its reads
+}
+
+// One tile of 16 agents through the network.  xb(c): this lane's B operand of
+// input chunk c (eight BF16 inputs 32 c + 8 g .. + 7 of agent col, zero beyond
+// the input length); w1(c, t), w2(c, t), w3(c): the layers' A operands;
+// hrow(col): row col of the wave's hidden tile in LDS, 64 BF16 starting
+// 16-byte aligned.  Returns the output pre-activations (z0, z1), biases
+// included, in the lanes with g == 0.
+template <class XB, class W1, class W2, class W3, class HR>
+__device__ __forceinline__ float2 mlp_tile(int kc, XB xb, W1 w1, W2 w2, W3 w3, const PolConsts &pc,
+                                          HR hrow, int lane) {
+    const int g = lane >> 4, col = lane & 15;
+    f32x4 acc[4];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const bf16x8 hb = *reinterpret_cast<const bf16x8 *>(s_hid + col * kHidLd + 32 * c + 8 * g);
+    for (int t = 0; t < 4; ++t) acc[t] = bias4(pc.b1, t, g);
+    for (int c = 0; c < kc; ++c) {
+        const bf16x8 x = xb(c);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2(c, t), hb, acc2[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1(c, t), x, acc[t], 0, 0, 0);
     }
-    float z0 = 0.0f, z1 = 0.0f;
+    store_hidden(acc, hrow, g, col);
+    bf16x8 hb[2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int c = 0; c < 2; ++c)
+        hb[c] = *reinterpret_cast<const bf16x8 *>(hrow(col) + 32 * c + 8 * g);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int h = 16 * t + 4 * g + r;
-            const float hv = tanh_fast(acc2[t][r] + pc.b2[h]);
-            z0 = z0 + hv * pc.w3[h];
-            z1 = z1 + hv * pc.w3[64 + h];
-        }
-    z0 = z0 + __shfl_xor(z0, 16, 64);
-    z1 = z1 + __shfl_xor(z1, 16, 64);
-    z0 = z0 + __shfl_xor(z0, 32, 64);
-    z1 = z1 + __shfl_xor(z1, 32, 64);
-    return make_float2(z0, z1);
+    for (int t = 0; t < 4; ++t) acc[t] = bias4(pc.b2, t, g);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2(c, t), hb[c], acc[t], 0, 0, 0);
+    store_hidden(acc, hrow, g, col);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        hb[c] = *reinterpret_cast<const bf16x8 *>(hrow(col) + 32 * c + 8 * g);
+    f32x4 z = g == 0 ? *reinterpret_cast<const f32x4 *>(pc.b3) : f32x4{};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3(c), hb[c], z, 0, 0, 0);
+    return make_float2(z[0], z[1]);
 }
 
 // The actor's action from the output pre-activations: the mean, tanh-squashed
 // and scaled to (max_turn, max_dspeed); with kSample, plus sigma * eps, and
 // the log density of the sample into *logp (when logp is not null).
 template <bool kSample>
-__device__ __forceinline__ float2 pol_output(float2 z, const PolConsts &pc, float max_turn,
-                                             float max_dspeed, float2 eps, float sig0, float sig1,
-                                             float logp_c, float *logp) {
-    float2 a = make_float2(max_turn * tanhf(z.x + pc.b3[0]), max_dspeed * tanhf(z.y + pc.b3[1]));
+__device__ __forceinline__ float2 pol_output(float2 z, float max_turn, float max_dspeed, float2 eps,
+                                             float sig0, float sig1, float logp_c, float *logp) {
+    float2 a = make_float2(max_turn * tanh_fast(z.x), max_dspeed * tanh_fast(z.y));
     if constexpr (kSample) {
         a.x = a.x + sig0 * eps.x;
         a.y = a.y + sig1 * eps.y;

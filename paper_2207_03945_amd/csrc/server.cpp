@@ -3,10 +3,8 @@
 // Episode requests (an env's parameters, its initial state and an episode
 // length) arrive at any time.  Each tick admits queued requests whose device
 // memory fits in the caller's arena, then runs ONE closed-loop batched step
-// (actions -> move -> view/reward -> FP64 returns -> the shared policy's next
-// actions, the policy running inside the view sweep) over every running
-// request, and retires the requests that reached their length.  A request's
-// first action comes from the sweep of its reset, at admission.  State
+// (shared policy -> actions -> move -> view/reward -> FP64 returns) over every
+// running request, and retires the requests that reached their length.  State
 // stays resident on the device for the whole episode (Sec. 2.2 of
 // arXiv:2207.03945: environment and learner exchange data on the device, with
 // no copy through the host); only the initial state goes up and the final
@@ -194,10 +192,7 @@ int try_admit(srv_t *S, Request &r) {
     r.rew = reinterpret_cast<float *>(io + align_up(n * 2 * sizeof(float), 256) +
                                       align_up(n * obs_dim_of(r.p) * sizeof(float), 256));
     rc = env_load_host_state(r.env, r.x.data(), r.y.data(), r.th.data(), r.s.data(), S->stream);
-    // the initial view, and the policy's first action from it, into the request's rows
-    PolFuse pf = policy_fuse_args(S->pol);
-    pf.act = reinterpret_cast<float2 *>(r.act);
-    if (rc == ENV_OK) rc = env_reset_policy(r.env, r.obs, pf, S->stream);
+    if (rc == ENV_OK) rc = env_reset(r.env, r.obs, S->stream);
     if (rc != ENV_OK) {
         release_request_blocks(S, r);
         return rc;
@@ -375,11 +370,11 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
     int rc = ENV_OK;
     if (S->dirty) rc = rebuild_plan(S);
     if (rc != ENV_OK) return rc;
-    // one launch sequence: each request's actions (computed by the previous
-    // view sweep) -> move -> view and reward -> the policy's next actions
-    PolFuse pf = policy_fuse_args(S->pol);
-    hipError_t e = launch_step(S->plan, S->table, 1, nullptr, nullptr, nullptr, 1, S->stream,
-                               nullptr, &pf);
+    // the policy on every running request's view (its own launch: run inside
+    // the view sweep it was measured slower), then one batched step
+    hipError_t e = policy_launch_envs(S->pol, S->plan, S->table, S->stream);
+    if (e == hipSuccess)
+        e = launch_step(S->plan, S->table, 1, nullptr, nullptr, nullptr, 1, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return set_error(ENV_EHIP, "srv_tick: %s", hipGetErrorString(e));
     for (int64_t id : S->running) env_advance(S->reqs.at(id).env, 1);

@@ -111,6 +111,7 @@ def lib():
         "env_set_sweep_lanes": (ctypes.c_int, [_P, ctypes.c_int]),
         "env_batch_set_sweep_lanes": (ctypes.c_int, [_P, ctypes.c_int]),
         "env_batch_get_sweep_lanes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+        "env_batch_set_policy_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
         "env_step_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_batch_run": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
         "env_batch_capture": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
@@ -322,6 +323,10 @@ class Batch:
     def set_sweep_lanes(self, lanes: int):
         """Lanes per agent in the batched sweep (1, 4, 16, 64; 0 = automatic)."""
         check(lib().env_batch_set_sweep_lanes(self.handle, int(lanes)))
+
+    def set_policy_fusion(self, on: bool):
+        """Run the policy inside the view sweep in step_policy / rollout (off by default)."""
+        check(lib().env_batch_set_policy_fusion(self.handle, 1 if on else 0))
 
     @property
     def sweep_lanes(self) -> int:

@@ -1,7 +1,7 @@
 """GPU policy network (BF16 MFMA, FP32 accumulate) against the FP64 oracle.
 
 Error bound.  With u = 2^-9 (half an ulp of BF16, relative) every input,
-weight and layer-1 activation carries a relative rounding of at most u, and
+weight and hidden activation carries a relative rounding of at most u, and
 FP32 accumulation adds at most K * 2^-24 relative.  Propagating first-order
 absolute errors through z = W^T h + b (tanh is 1-Lipschitz) gives, per agent
 and unit, with dh the error of the layer input (its own BF16 rounding
@@ -36,7 +36,7 @@ def error_bound(obs, ws, bs, scale=(0.2, 0.1)):
         k = w.shape[0]
         dz = dh @ aw + (U_BF16 + k * 2.0 ** -24) * (np.abs(h) @ aw) + 1e-6
         h = np.tanh(h @ w + b)
-        dh = dz + (U_BF16 * np.abs(h) if layer < len(ws) - 2 else 0.0)  # h1 re-rounded to BF16
+        dh = dz + (U_BF16 * np.abs(h) if layer < len(ws) - 1 else 0.0)  # hidden layers re-rounded to BF16
     return dh * np.asarray(scale)
 
 
@@ -153,13 +153,15 @@ def test_policy_staged_and_direct_loads_agree_bitwise(in_dim):
 
 
 @pytest.mark.parametrize("kind,lanes", [("v16", 0), ("v16", 1), ("v16", 4), ("v16", 64),
-                                        ("v8", 16), ("paper129", 16), ("paper129", 1)])
+                                        ("v8", 16), ("v8", 1), ("paper129", 16), ("paper129", 1),
+                                        ("paper129", 4)])
 def test_fused_policy_step_equals_forward_then_step(kind, lanes):
-    """env_step_policy runs the policy inside the view sweep (the next step's
-    actions come from the views still on chip): over six steps its actions,
-    views and rewards equal pol_forward + env_step_batched bitwise, for each
-    sweep lane count and view kind; the cached next actions are recomputed
-    when the obs pointer changes and when an env's state is set anew."""
+    """env_step_policy with policy fusion on (the next step's actions come from
+    the views still on chip when the sweep has one or four lanes per agent; a
+    separate launch with 16 or 64): over six steps its actions, views and
+    rewards equal pol_forward + env_step_batched bitwise, for each sweep lane
+    count and view kind; the cached next actions are recomputed when the obs
+    pointer changes and when an env's state is set anew."""
     if kind == "paper129":
         ps = [flock.Params(n_agents=n, box=100.0, radius=10.0, sectors=128,
                            fov=math.radians(250.0), flags=flock.ENV_FLAG_SPEED_OBS)
@@ -183,6 +185,7 @@ def test_fused_policy_step_equals_forward_then_step(kind, lanes):
         if lanes:
             b.set_sweep_lanes(lanes)
         pair.append((envs, b, obs))
+    pair[0][1].set_policy_fusion(True)
     (envs_a, ba, obs_a), (envs_b, bb, obs_b) = pair
     G = ba.n
     act_a = torch.empty(G, 2, device="cuda")

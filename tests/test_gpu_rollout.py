@@ -51,7 +51,7 @@ def net_error_bound(obs, ws, bs, linear_out):
         z = h @ w + b
         last = layer == n_layers - 1
         h = z if (last and linear_out) else np.tanh(z)
-        dh = dz + (U_BF16 * np.abs(h) if layer < n_layers - 2 else 0.0)
+        dh = dz + (U_BF16 * np.abs(h) if layer < n_layers - 1 else 0.0)
     return dh
 
 
@@ -115,7 +115,12 @@ def _make(ps, states):
     return envs
 
 
-def test_rollout_equals_stepwise_and_oracle_teacher_forced():
+@pytest.mark.parametrize("fuse,lanes", [(False, 0), (True, 1), (True, 4)],
+                         ids=["separate", "fused-1-lane", "fused-4-lanes"])
+def test_rollout_equals_stepwise_and_oracle_teacher_forced(fuse, lanes):
+    """The rollout against the same steps taken one call at a time, bitwise,
+    with the policy launched separately or run inside the view sweep (one lane
+    per agent: 129 inputs in five chunks; four lanes: the block-barrier path)."""
     sizes = [700, 1000, 37]
     ps, states = _paper_envs(sizes, seed=4)
     T = 8
@@ -126,6 +131,9 @@ def test_rollout_equals_stepwise_and_oracle_teacher_forced():
         e_r.reset()
         e_s.reset()
     br, bs_ = flock.Batch(envs_r), flock.Batch(envs_s)
+    br.set_policy_fusion(fuse)
+    if lanes:
+        br.set_sweep_lanes(lanes)
     G, off = br.n, br.offsets
     eps = dev(workloads.policy_noise(T, G, seed=5))
     obs_buf = torch.empty(T + 1, G, d, device="cuda")

@@ -154,7 +154,7 @@ def _act_bound(obs, ws, bs):
         aw = np.abs(w)
         dz = dh @ aw + (U_BF16 + w.shape[0] * 2.0 ** -24) * (np.abs(h) @ aw) + 1e-6
         h = np.tanh(h @ w + b)
-        dh = dz + (U_BF16 * np.abs(h) if layer < len(ws) - 2 else 0.0)
+        dh = dz + (U_BF16 * np.abs(h) if layer < len(ws) - 1 else 0.0)
     return dh * np.array([0.2, 0.1])
 
 

@@ -173,6 +173,15 @@ struct EnvLayout {
     size_t bytes;
 };
 
+// Strips of an env's own step (a plan of one env), 0 when the strip sort is
+// not allowed for it.
+int64_t env_own_strips(const env_params_t &p, const Geometry &gm) {
+    DevEnv d = make_desc(p, gm);
+    if (!strips_allowed(d)) return 0;
+    DevEnv *tabs[1] = {&d};
+    return assign_strips(tabs, 1, 1, p.n_agents, nullptr);
+}
+
 EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
     EnvLayout l;
     Carver cv{base, 0};
@@ -185,7 +194,7 @@ EnvLayout carve_env(char *base, const env_params_t &p, const Geometry &gm) {
     const bool counts = (p.flags & ENV_FLAG_COUNTS) != 0;
     l.nb = counts ? cv.take<int32_t>(n) : nullptr;
     l.col = counts ? cv.take<int32_t>(n) : nullptr;
-    carve_sort(cv, n, (int64_t)gm.ncx * gm.ncy, 1, &l.sort);
+    carve_sort(cv, n, (int64_t)gm.ncx * gm.ncy, 1, &l.sort, env_own_strips(p, gm));
     l.bytes = align_up(cv.off, 256);
     return l;
 }
@@ -220,6 +229,7 @@ struct flock_env {
     int32_t base_host[2];   // {0, n}
     int parity = 0;         // index of the current record buffer
     uint64_t gen = 0;       // bumped by every call that changes the state
+    bool sorted = false;    // records in cell order (after a sort; not after set_state)
     bool has_state = false;
     bool reset_done = false;
     bool uploaded = false;
@@ -269,6 +279,7 @@ struct flock_batch {
     std::vector<DevEnv> tab[2];      // [t]: env k has buffer base_par[k] ^ t current
     std::vector<int32_t> base;
     std::vector<int64_t> off;
+    std::vector<int32_t> strip_env;  // env of each strip (strip sort)
     StepPlan plan;
     bool uploaded = false;
     GraphCache gc[2];                // K-step graphs by starting table
@@ -296,6 +307,8 @@ int64_t cell_count_for(const env_params_t &p) {
     const Geometry g = geometry(p);
     return (int64_t)g.ncx * g.ncy;
 }
+
+int64_t column_count_for(const env_params_t &p) { return geometry(p).ncx; }
 
 // The stencil's area before trimming to the disc: 2 reach + 1 columns, each
 // 2 radius + one row high.
@@ -338,13 +351,17 @@ int env_parity(const env_t *env) { return env->parity; }
 
 void env_advance(env_t *env, int steps) {
     env->parity ^= (steps & 1);
+    env->sorted = true;
     ++env->gen;
 }
+
+bool env_sorted(const env_t *env) { return env->sorted; }
 
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s) {
     const int n = env->p.n_agents;
     env->has_state = true;
+    env->sorted = false;
     ++env->gen;
     if (n == 0) return ENV_OK;
     // Stage the agent-order arrays in the next buffer's record area (free
@@ -369,10 +386,10 @@ int env_returns_to(env_t *env, double *out, hipStream_t s) {
     return ENV_OK;
 }
 
-size_t sort_scratch_bytes(int64_t G, int64_t C, int E) {
+size_t sort_scratch_bytes(int64_t G, int64_t C, int E, int64_t S) {
     Carver cv{nullptr, 0};
     SortArrays a;
-    carve_sort(cv, G, C, E, &a);
+    carve_sort(cv, G, C, E, &a, S);
     return align_up(cv.off, 256);
 }
 
@@ -445,6 +462,11 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->scalars = make_desc(*p, gm);
     e->scalars.nb = e->lay.nb;
     e->scalars.col = e->lay.col;
+    const int64_t own_strips = env_own_strips(*p, gm);
+    if (own_strips > 0) {
+        DevEnv *tabs[1] = {&e->scalars};
+        assign_strips(tabs, 1, 1, p->n_agents, nullptr);
+    }
     e->own[0] = orient(e, 0);
     e->own[1] = orient(e, 1);
     e->base_host[0] = 0;
@@ -460,6 +482,8 @@ int env_create(const env_params_t *p, void *workspace, size_t bytes, env_t **out
     e->plan.lanes = auto_lanes(env_candidates_per_agent(e), p->sectors, p->n_agents);
     e->plan.max_env_cells = e->plan.C;
     e->plan.env_sort_recs = 0;  // one env: the multi-block kernels fill the GPU better
+    e->plan.strips = (int)own_strips;
+    if (own_strips > 0) plan_strip_launch(&e->plan, &e->scalars, 1);
     e->plan.scan_blocks = scan_blocks_for(e->plan.C, e->plan.C);
     *out = e;
     g_err.clear();
@@ -496,6 +520,7 @@ int env_set_state(env_t *env, const float *x, const float *y, const float *th, c
                                      env->lay.id[env->parity], n, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_set_state");
     env->has_state = true;
+    env->sorted = false;
     ++env->gen;
     return ENV_OK;
 }
@@ -523,10 +548,12 @@ int env_reset(env_t *env, float *obs, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "env_reset: zero returns");
     // The sense-only pass yields no reward: the episode's first reward comes
     // with the first step.  It sorts the records into cell order.
+    env->plan.strip_now = env->sorted ? 1 : 0;
     e = launch_step(env->plan, env->parity, 0, nullptr, obs, nullptr, 0, s);
     if (e != hipSuccess) return hip_fail(e, "env_reset: sense");
     if (n > 0) env->parity ^= 1;
     env->reset_done = true;
+    env->sorted = true;
     ++env->gen;
     return ENV_OK;
 }
@@ -536,9 +563,11 @@ int env_step(env_t *env, const float *act, float *obs, float *reward, void *stre
     if (!env->reset_done) return fail(ENV_ESTATE, "env_step before env_reset");
     const int n = env->p.n_agents;
     if (n > 0 && (!act || !obs || !reward)) return fail(ENV_EINVAL, "act/obs/reward is NULL");
+    env->plan.strip_now = env->sorted ? 1 : 0;
     hipError_t e = launch_step(env->plan, env->parity, 1, act, obs, reward, 1, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "env_step");
     if (n > 0) env->parity ^= 1;
+    env->sorted = true;
     ++env->gen;
     return ENV_OK;
 }
@@ -619,7 +648,7 @@ size_t env_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 int env_step_static(env_t *env, const float *act, float *obs, float *reward, void *stream) {
     if (!env) return fail(ENV_EINVAL, "env is NULL");
-    const size_t need = sort_scratch_bytes(env->plan.G, env->plan.C, 1);
+    const size_t need = sort_scratch_bytes(env->plan.G, env->plan.C, 1, env->plan.strips);
     if (need > kStaticScratchBytes)
         return fail(ENV_ENOMEM,
                     "env_step_static: a step of %lld agents over %lld cells needs %zu bytes of "
@@ -634,12 +663,14 @@ int env_step_static(env_t *env, const float *act, float *obs, float *reward, voi
     if (rc != ENV_OK) return rc;
     StepPlan p = env->plan;
     Carver cv{static_cast<char *>(base), 0};
-    carve_sort(cv, p.G, p.C, 1, &p.a);
+    carve_sort(cv, p.G, p.C, 1, &p.a, p.strips);
+    p.strip_now = env->sorted ? 1 : 0;
     hipStream_t s = as_stream(stream);
     hipError_t e = launch_bind_one(p, env->own[0], env->own[1], n, s);
     if (e == hipSuccess) e = launch_step(p, env->parity, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_static");
     env->parity ^= 1;
+    env->sorted = true;
     ++env->gen;
     return ENV_OK;
 }
@@ -678,11 +709,24 @@ static int batch_layout(env_t *const *envs, int n_envs, std::vector<int32_t> *ba
     return ENV_OK;
 }
 
+// Strips of a batch's envs (the strip sort), 0 when some env does not allow it.
+static int64_t batch_strips(env_t *const *envs, int n_envs, int64_t G,
+                            std::vector<int32_t> *strip_env) {
+    std::vector<DevEnv> d(n_envs);
+    for (int k = 0; k < n_envs; ++k) {
+        d[k] = envs[k]->scalars;
+        if (!strips_allowed(d[k])) return 0;
+    }
+    DevEnv *tabs[1] = {d.data()};
+    return assign_strips(tabs, 1, n_envs, G, strip_env);
+}
+
 size_t env_batch_workspace_bytes(env_t *const *envs, int n_envs) {
     int64_t G, C;
     int v;
     if (batch_layout(envs, n_envs, nullptr, nullptr, &G, &C, &v) != ENV_OK) return 0;
-    return sort_scratch_bytes(G, C, n_envs) + align_up((size_t)G * sizeof(float2), 256);
+    const int64_t S = batch_strips(envs, n_envs, G, nullptr);
+    return sort_scratch_bytes(G, C, n_envs, S) + align_up((size_t)G * sizeof(float2), 256);
 }
 
 static int batch_auto_lanes(const std::vector<env_t *> &envs) {
@@ -715,7 +759,8 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
         }
     }
     Carver cv{static_cast<char *>(ws), 0};
-    carve_sort(cv, G, C, n_envs, &b->plan.a);
+    const int64_t S = batch_strips(envs, n_envs, G, &b->strip_env);
+    carve_sort(cv, G, C, n_envs, &b->plan.a, S);
     b->act_next = cv.take<float2>((size_t)G);
     if (bytes < align_up(cv.off, 256)) {
         delete b;
@@ -740,6 +785,14 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes, env
     b->plan.max_env_cells = max_cells;
     b->plan.env_sort_recs = env_sort_recs_for(n_envs, max_agents, max_cells);
     b->plan.scan_blocks = scan_blocks_for(C, max_cells);
+    b->plan.strips = (int)S;
+    if (S > 0) {
+        std::vector<DevEnv> d(n_envs);
+        for (int k = 0; k < n_envs; ++k) d[k] = envs[k]->scalars;
+        DevEnv *tabs[1] = {d.data()};
+        assign_strips(tabs, 1, n_envs, G, nullptr);
+        plan_strip_launch(&b->plan, d.data(), n_envs);
+    }
     *out = b;
     return ENV_OK;
 }
@@ -815,6 +868,10 @@ static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
         c += (int64_t)b->envs[k]->gm.ncx * b->envs[k]->gm.ncy;
         b->base_par[k] = b->envs[k]->parity;
     }
+    if (b->plan.strips > 0) {
+        DevEnv *tabs[2] = {b->tab[0].data(), b->tab[1].data()};
+        assign_strips(tabs, 2, E, b->plan.G, nullptr);
+    }
     hipError_t e = hipSuccess;
     for (int f = 0; f < 2 && e == hipSuccess; ++f)
         e = hipMemcpyAsync(b->plan.a.envs[f], b->tab[f].data(), E * sizeof(DevEnv),
@@ -822,6 +879,9 @@ static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->plan.a.base, b->base.data(), b->base.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !b->uploaded && b->plan.strips > 0)
+        e = hipMemcpyAsync(b->plan.a.strip_env, b->strip_env.data(),
+                           b->strip_env.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !b->uploaded) e = launch_clear(b->plan, s);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
     b->uploaded = true;
@@ -835,9 +895,18 @@ static int batch_prepare(env_batch_t *b, hipStream_t s, int *table) {
 static void batch_advance(env_batch_t *b, int steps) {
     for (env_t *e : b->envs) {
         e->parity ^= (steps & 1);
+        e->sorted = true;
         ++e->gen;
     }
     b->next_valid = false;
+}
+
+// Whether this launch's first step may use the strip sort (every env's
+// records in cell order); later steps of a launch always may.
+static int batch_sorted(const env_batch_t *b) {
+    for (const env_t *e : b->envs)
+        if (!e->sorted) return 0;
+    return 1;
 }
 
 int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward, void *stream) {
@@ -847,6 +916,7 @@ int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward
     int t;
     int rc = batch_prepare(b, s, &t);
     if (rc != ENV_OK) return rc;
+    b->plan.strip_now = batch_sorted(b);
     hipError_t e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_batched");
     batch_advance(b, 1);
@@ -869,6 +939,7 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
     }
     for (int k = 0; k < 4; ++k) phase_ms[k] = 0.0f;
     if (b->plan.G == 0) return ENV_OK;
+    b->plan.strip_now = batch_sorted(b);
     hipError_t e = launch_step(b->plan, t, 1, act, obs, reward, 1, s, b->events);
     if (e != hipSuccess) return hip_fail(e, "env_step_batched_timed");
     batch_advance(b, 1);
@@ -894,12 +965,17 @@ static int batch_capture(env_batch_t *b, int k_steps, const float *act, float *o
     if (rc != ENV_OK) return rc;
     *table = t;
     const int64_t G = b->plan.G;
+    // the first step may sort by strips only if every env is in cell order;
+    // the steps after it always may
+    StepPlan first = b->plan, later = b->plan;
+    first.strip_now = batch_sorted(b);
+    later.strip_now = 1;
     std::vector<uint64_t> key = {(uint64_t)k_steps, key_of(act), key_of(obs), key_of(reward),
-                                 key_of(s)};
+                                 key_of(s), (uint64_t)first.strip_now};
     return capture_graph(b->gc[t], std::move(key), s, [&]() {
         hipError_t le = hipSuccess;
         for (int k = 0; k < k_steps && le == hipSuccess; ++k)
-            le = launch_step(b->plan, t ^ (k & 1), 1, act + (size_t)k * G * 2, obs,
+            le = launch_step(k == 0 ? first : later, t ^ (k & 1), 1, act + (size_t)k * G * 2, obs,
                              reward + (size_t)k * G, 1, s);
         return le;
     });
@@ -966,6 +1042,10 @@ static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, co
                                  key_of(s), ((uint64_t)lsb[0] << 32) | lsb[1],
                                  ((uint64_t)lsb[2] << 32) | lsb[3]};
     const bool fuse_plan = !tag && b->fuse_policy && plan_fuses_policy(b->plan);
+    StepPlan first = b->plan, later = b->plan;
+    first.strip_now = batch_sorted(b);
+    later.strip_now = 1;
+    key.push_back((uint64_t)first.strip_now);
     rc = capture_graph(b->rgc[t], std::move(key), s, [&]() {
         hipError_t le = hipSuccess;
         for (int k = 0; k < steps && le == hipSuccess; ++k) {
@@ -994,7 +1074,7 @@ static int rollout_impl(env_batch_t *b, pol_t *pol, pol_t *chaser, int steps, co
                                          logp ? logp + (size_t)(k + 1) * G : nullptr);
             }
             if (le == hipSuccess)
-                le = launch_step(b->plan, tk, 1, a_k, obs + (size_t)(k + 1) * G * d,
+                le = launch_step(k == 0 ? first : later, tk, 1, a_k, obs + (size_t)(k + 1) * G * d,
                                  reward + (size_t)k * G, 1, s, nullptr, fuse ? &pf : nullptr);
         }
         return le;
@@ -1038,6 +1118,7 @@ int env_step_policy_tag(env_batch_t *b, pol_t *runner, pol_t *chaser, float *act
     hipError_t e = policy_launch_typed(runner, b->plan, t, 0, obs, nullptr, nullptr, act, nullptr, s);
     if (e == hipSuccess)
         e = policy_launch_typed(chaser, b->plan, t, 1, obs, nullptr, nullptr, act, nullptr, s);
+    b->plan.strip_now = batch_sorted(b);
     if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "env_step_policy_tag");
     batch_advance(b, 1);
@@ -1060,6 +1141,7 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
     if (!b->fuse_policy || !plan_fuses_policy(b->plan)) {
         // the policy as its own launch before the step
         hipError_t e = policy_launch(pol, obs, b->plan.G, act, s);
+        b->plan.strip_now = batch_sorted(b);
         if (e == hipSuccess) e = launch_step(b->plan, t, 1, act, obs, reward, 1, s);
         if (e != hipSuccess) return hip_fail(e, "env_step_policy");
         batch_advance(b, 1);
@@ -1075,6 +1157,7 @@ int env_step_policy(env_batch_t *b, pol_t *pol, float *act, float *obs, float *r
     // view sweep writes the next step's actions there
     PolFuse pf = policy_fuse_args(pol);
     pf.act = b->act_next;
+    b->plan.strip_now = batch_sorted(b);
     if (e == hipSuccess) e = launch_step(b->plan, t, 1, nxt, obs, reward, 1, s, nullptr, &pf, act);
     if (e != hipSuccess) {
         b->next_valid = false;

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "flockenv.h"
 #include "policy_tile.h"
 
@@ -56,8 +58,12 @@ struct DevEnv {
     int32_t tag;                 // tag environment (runners and chasers)
     int32_t n_chasers;           // tag: agents 0 .. n_chasers-1 are chasers
     float r_catch;               // tag: chaser reward per runner touched
+    // Column strips of the strip sort (per plan): strips strip_base ..
+    // strip_base + n_strips - 1 of the plan, strip_cols columns each (the
+    // last takes the remainder).
+    int32_t strip_base, strip_cols, n_strips;
 };
-static_assert(sizeof(DevEnv) <= 192, "DevEnv grew");
+static_assert(sizeof(DevEnv) <= 256, "DevEnv grew");
 
 // Device scratch of one counting sort over G agents and C cells.
 struct SortArrays {
@@ -71,6 +77,11 @@ struct SortArrays {
     int32_t *part;     // [scan partials]
     DevEnv *envs[2];   // [E] descriptor tables: [0] as stored, [1] buffers swapped
     int32_t *base;     // [E + 1] agent_base of each env, then G
+    // Strip sort (S strips): env of each strip, and the strips' look-back
+    // words then the block ticket counter (S + 1 words, zero between steps).
+    int32_t *strip_env;  // [S]
+    uint32_t *status;    // [S + 1]
+    int32_t n_status;    // S + 1 (0 without strips)
 };
 
 // The shared policy evaluated inside a step's view sweep, on the view the
@@ -105,6 +116,10 @@ struct StepPlan {
     int scan_blocks;  // 0 -> one scan block per env (every env <= 16384 cells)
     int64_t max_env_cells;  // cells of the plan's largest env
     int env_sort_recs;      // > 0: one block per env does move to scatter (records per thread)
+    int strips;             // > 0: the envs' column strips (the strip sort is allowed)
+    int strip_now;          // this launch may use the strip sort (every env's records sorted)
+    int strip_cells;        // cells of the plan's largest strip
+    int strip_cap;          // agents a strip block lists in LDS (more: a second pass)
 };
 
 // Workspace carving --------------------------------------------------------
@@ -130,8 +145,26 @@ int scan_blocks_for(int64_t C, int64_t max_env_cells);
 // Records per thread of the per-env fused sort for this plan shape, or 0 when
 // the envs are too few to fill the GPU or too large for one block.
 int env_sort_recs_for(int n_envs, int64_t max_env_agents, int64_t max_env_cells);
-// Carve the sort scratch for G agents, C cells and E envs.
-void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a);
+// Carve the sort scratch for G agents, C cells, E envs and S strips.
+void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a, int64_t S = 0);
+// Strip sort: one block per strip of columns of one env moves the agents of
+// its columns and of the two next to them (an agent moves at most one
+// column per step), keeps those now in its strip, ranks them by cell in LDS,
+// takes its output offset from the strips before it (look-back), and writes
+// them in cell order with the strip's cell starts.  Allowed for an env when
+// its records are in cell order, its speed limit is at most half a column
+// and a strip's cells fit the block's LDS.
+constexpr int kStripCells = 8192;
+bool strips_allowed(const DevEnv &d);
+// Strip width of an env for a plan of G agents in all: columns per strip.
+int strip_cols_for(const DevEnv &d, int64_t G);
+// Assign strips to the envs' descriptors (in order); returns S and fills
+// strip_env with the env index of each strip.
+int64_t assign_strips(DevEnv *const *tabs, int n_tabs, int n_envs, int64_t G,
+                      std::vector<int32_t> *strip_env);
+// Fill the plan's strip_cells / strip_cap from its envs'
+// descriptors (after assign_strips) and its strip count.
+void plan_strip_launch(StepPlan *p, const DevEnv *envs, int n_envs);
 
 // Launchers (return hipSuccess or the first error) ------------------------
 // Zero the cell counts (used once after carving).
@@ -193,16 +226,18 @@ int auto_lanes(double cand, int v, int64_t agents);
 DevEnv env_descriptor(const env_t *env, int flip);
 int64_t env_cell_count(const env_t *env);       // cells of this env's grid
 int64_t cell_count_for(const env_params_t &p);  // cells an env of these params uses
+int64_t column_count_for(const env_params_t &p); // grid columns of such an env
 const env_params_t &env_params(const env_t *env);
 int env_parity(const env_t *env);
 void env_advance(env_t *env, int steps);        // record `steps` stepped elsewhere
+bool env_sorted(const env_t *env);              // records in cell order (strip sort allowed)
 // Copy a host state into the env (async on s; host arrays must outlive the copy).
 int env_load_host_state(env_t *env, const float *x, const float *y, const float *th,
                         const float *s_, hipStream_t s);
 // Device FP64 returns of the env in agent order, into `out` (device [n]).
 int env_returns_to(env_t *env, double *out, hipStream_t s);
-// Bytes of the batch sort scratch for G agents, C cells, E envs.
-size_t sort_scratch_bytes(int64_t G, int64_t C, int E);
+// Bytes of the batch sort scratch for G agents, C cells, E envs, S strips.
+size_t sort_scratch_bytes(int64_t G, int64_t C, int E, int64_t S = 0);
 
 // Policy network (policy_mfma.hip) ---------------------------------------------
 // act[n][2] = policy(obs[n][in_dim]) on `s`.

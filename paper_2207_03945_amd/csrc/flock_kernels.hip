@@ -40,6 +40,9 @@
 //   * view: 1 - sqrt(d^2_min) * (1/R), within a few ulp of 1 - d_min/R.
 #include <limits.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include <type_traits>
 
 #include "flock_internal.h"
@@ -609,6 +612,264 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
     }
 }
 
+// ------------------------------------------------------------- strip sort
+
+// One block per strip of columns of one env (see carve_sort and the plan's
+// strips in flock_internal.h).  The records are in cell order (column
+// major), so the records of a range of columns are one range of records,
+// found by a search; an agent moves at most one column per step, so the
+// agents now in the strip were, before the move, in its columns or in the one
+// on either side.  The block moves those (twice: once to count, once to
+// place, reading the records again from cache instead of keeping a variable
+// number of them), ranks its agents by cell in LDS, takes its first output
+// row from the strips of the env before it by decoupled look-back, and
+// writes its agents in cell order and its cells' starts.
+constexpr int kStripNT = 512;
+constexpr int kStripR = 4;  // old records per thread and round
+constexpr uint32_t kStripAgg = 1u << 30;   // look-back word: the strip's own count is set
+constexpr uint32_t kStripIncl = 1u << 31;  // the count of the env's strips up to this one is set
+constexpr uint32_t kStripVal = kStripAgg - 1;
+// Bound on one look-back wait.  Blocks take their strips in ticket order, so
+// a strip waits only for strips already running, which never wait for it:
+// the bound is never reached (it keeps a broken invariant from hanging).
+constexpr int kStripSpin = 1 << 20;
+
+// First record of env E (cell order) whose column is >= col; n when col >=
+// ncx.  Every lane of the calling wave takes part: each round probes 64
+// evenly spaced records of the remaining range (columns are nondecreasing, so
+// the probes below col form a prefix of the lanes).
+__device__ int wave_first_col(const DevEnv &E, int col) {
+    if (col <= 0) return 0;
+    if (col >= E.ncx) return E.n;
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = E.n;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int step = (hi - lo + 63) >> 6;
+        const int q = lo + lane * step;
+        const bool below = q < hi && cell_of(E.rec_cur[q].x, E.inv_cx, E.ncx) < col;
+        const uint64_t m = __ballot(below);
+        const int k = m ? 64 - __builtin_clzll(m) : 0;  // probes below col
+        if (k == 0) break;                              // record lo is at or past col
+        const int next = lo + k * step;                 // first probe not below (or past hi)
+        lo = lo + (k - 1) * step + 1;
+        hi = next < hi ? next : hi;
+    }
+    return lo;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *__restrict__ envs,
+                                                   int n_envs, int C, int G, int S, int do_move,
+                                                   const float2 *__restrict__ act, int tag,
+                                                   float2 *__restrict__ act_copy, int cap,
+                                                   int direct) {
+    // dynamic LDS: the strip's cells (counts, then each cell's next free row),
+    // then up to `cap` of its agents: old record, cell, action
+    extern __shared__ int s_dyn[];
+    __shared__ int s_wave[NT / 64 + 1];
+    __shared__ int s_tk, s_base, s_own;
+    __shared__ int s_rng[4];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // with few strips every block is resident at once and the block index
+        // serves; otherwise a ticket makes strips start in order
+        s_tk = direct ? (int)blockIdx.x : (int)atomicAdd(&a.status[S], 1u);
+        s_own = 0;
+    }
+    __syncthreads();
+    const int t = s_tk;
+    const DevEnv &E = envs[n_envs == 1 ? 0 : a.strip_env[t]];
+    const int ls = t - E.strip_base, nst = E.n_strips, ncx = E.ncx, ncy = E.ncy, n = E.n;
+    const int c0 = ls * E.strip_cols, c1 = ls == nst - 1 ? ncx : c0 + E.strip_cols;
+    const int cbase = c0 * ncy, ncell = (c1 - c0) * ncy;
+    int *s_cells = s_dyn;
+    int *s_oi = s_dyn + ((ncell + 3) & ~3);
+    int *s_oc = s_oi + cap;
+    float2 *s_oa = reinterpret_cast<float2 *>(s_oc + cap);
+    for (int c = tid; c < ncell; c += NT) s_cells[c] = 0;
+    // old records of columns c0 - 1 .. c1 (periodic): all of them when those
+    // columns cover the box, else one range or two (wrapping); waves 0 and 1
+    // search one boundary each
+    if (tid == 0) {
+        s_rng[0] = 0;
+        s_rng[1] = n;
+        s_rng[2] = 0;
+        s_rng[3] = 0;
+    }
+    __syncthreads();
+    if (nst > 1 && c1 - c0 + 2 < ncx && tid < 128) {
+        const int w = tid >> 6;
+        int col, slot;
+        if (c0 == 0) {
+            col = w == 0 ? ncx - 1 : c1 + 1;
+            slot = w == 0 ? 0 : 3;
+        } else if (c1 == ncx) {
+            col = w == 0 ? c0 - 1 : 1;
+            slot = w == 0 ? 0 : 3;
+        } else {
+            col = w == 0 ? c0 - 1 : c1 + 1;
+            slot = w == 0 ? 0 : 1;
+        }
+        const int r = wave_first_col(E, col);
+        if ((tid & 63) == 0) s_rng[slot] = r;
+    }
+    __syncthreads();
+    // kStripR old records per thread and round, all loads issued before any
+    // is used (each record's action is a gather by its id); each record is
+    // moved as in k_env_sort
+    constexpr int R = kStripR;
+    auto round = [&](int i0, int i1, auto use) {
+        int id[R];
+        float4 m[R];
+        float2 av[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = i0 + u * NT;
+            id[u] = i < i1 ? E.id_cur[i] : 0;
+            m[u] = i < i1 ? E.rec_cur[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = i0 + u * NT;
+            av[u] = make_float2(0.0f, 0.0f);
+            if (do_move && i < i1)
+                av[u] = act ? act[E.agent_base + id[u]]
+                            : reinterpret_cast<const float2 *>(E.act)[id[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = i0 + u * NT;
+            if (i >= i1) continue;
+            const float4 mm = do_move ? move_record(E, m[u], av[u]) : m[u];
+            const int cx = cell_of(mm.x, E.inv_cx, ncx);
+            if (cx >= c0 && cx < c1)
+                use(i, mm, id[u], av[u], cx * ncy + cell_of(mm.y, E.inv_cy, ncy) - cbase);
+        }
+    };
+    auto each_old = [&](auto use) {
+        for (int r = 0; r < 4; r += 2)
+            for (int i0 = s_rng[r] + tid; i0 < s_rng[r + 1]; i0 += R * NT)
+                round(i0, s_rng[r + 1], use);
+    };
+    // pass 1: count the strip's agents per cell, listing the first `cap` of them
+    each_old([&](int i, const float4 &, int, float2 av, int cell) {
+        atomicAdd(&s_cells[cell], 1);
+        const int k = atomicAdd(&s_own, 1);
+        if (k < cap) {
+            s_oi[k] = i;
+            s_oc[k] = cell;
+            s_oa[k] = av;
+        }
+    });
+    __syncthreads();
+    // exclusive scan of the counts: thread t owns cells [t k, t k + k)
+    const int per = (ncell + NT - 1) / NT;
+    const int q0 = tid * per;
+    int sum = 0;
+    for (int c = q0; c < q0 + per && c < ncell; ++c) sum += s_cells[c];
+    int total;
+    int run = block_exclusive_scan<NT>(sum, s_wave, &total);
+    for (int c = q0; c < q0 + per && c < ncell; ++c) {
+        const int cnt = s_cells[c];
+        s_cells[c] = run;
+        run += cnt;
+    }
+    if (tid < 64) {
+        // the env's agents before this strip: decoupled look-back over the
+        // env's earlier strips, 64 of them per round (lane k reads strip
+        // t - 1 - k): the counts down to the nearest strip whose running total
+        // is set, once every one of them has published
+        uint32_t *st = a.status;
+        const int lane = tid;
+        int base = 0;
+        if (ls == 0) {
+            if (lane == 0)
+                __hip_atomic_store(&st[t], kStripIncl | (uint32_t)total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(&st[t], kStripAgg | (uint32_t)total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int top = t - 1, spins = 0;
+            while (spins < kStripSpin) {
+                const int j = top - lane;
+                const bool valid = j >= E.strip_base;
+                const uint32_t w = valid ? __hip_atomic_load(&st[j], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)
+                                         : 0u;
+                const uint64_t incl = __ballot(valid && (w & kStripIncl));
+                const uint64_t ready = __ballot(valid && (w & (kStripIncl | kStripAgg)));
+                const uint64_t need = incl ? (incl & (~incl + 1)) * 2 - 1  // lanes up to the nearest total
+                                           : __ballot(valid);
+                if ((ready & need) != need) {
+                    ++spins;
+                    continue;
+                }
+                int v = ((need >> lane) & 1) ? (int)(w & kStripVal) : 0;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+                base += v;
+                if (incl) break;
+                top -= 64;
+            }
+            if (lane == 0)
+                __hip_atomic_store(&st[t], kStripIncl | (uint32_t)(base + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            s_base = base;
+            if (t == S - 1) a.start[C] = G;
+        }
+    }
+    __syncthreads();
+    const int base = s_base;
+    for (int c = tid; c < ncell; c += NT) a.start[E.cell_base + cbase + c] = E.agent_base + base + s_cells[c];
+    __syncthreads();  // the starts are read before the counts become row cursors
+    // place the strip's agents: from the list (one load round: record, id,
+    // return), or, when the strip holds more than `cap`, by a second pass
+    auto place = [&](int i, const float4 &m, int id, float2 av, int cell) {
+        const int j = base + atomicAdd(&s_cells[cell], 1);
+        E.rec_nxt[j] = m;
+        E.id_nxt[j] = id;
+        E.ret_nxt[j] = E.ret_cur[i];
+        a.sxy[E.agent_base + j] = make_float2(m.x, m.y);
+        if (tag) a.stype[E.agent_base + j] = id < E.n_chasers ? 1 : 0;
+        if (do_move && act_copy) act_copy[E.agent_base + id] = av;
+    };
+    const int own = s_own;
+    if (own <= cap) {
+        for (int k0 = tid; k0 < own; k0 += R * NT) {
+            int oi[R], id[R];
+            float4 m[R];
+            double ret[R];
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int k = k0 + u * NT;
+                oi[u] = k < own ? s_oi[k] : 0;
+                id[u] = k < own ? E.id_cur[oi[u]] : 0;
+                m[u] = k < own ? E.rec_cur[oi[u]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                ret[u] = k < own ? E.ret_cur[oi[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int k = k0 + u * NT;
+                if (k >= own) continue;
+                const float2 av = s_oa[k];
+                const float4 mm = do_move ? move_record(E, m[u], av) : m[u];
+                const int j = base + atomicAdd(&s_cells[s_oc[k]], 1);
+                E.rec_nxt[j] = mm;
+                E.id_nxt[j] = id[u];
+                E.ret_nxt[j] = ret[u];
+                a.sxy[E.agent_base + j] = make_float2(mm.x, mm.y);
+                if (tag) a.stype[E.agent_base + j] = id[u] < E.n_chasers ? 1 : 0;
+                if (do_move && act_copy) act_copy[E.agent_base + id[u]] = av;
+            }
+        }
+    } else {
+        each_old(place);
+    }
+}
+
 // ------------------------------------------------------------------ scatter
 
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArrays a, const DevEnv *__restrict__ envs,
@@ -927,6 +1188,9 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     int *s_pe = reinterpret_cast<int *>(s_min + PL.env);
     int *s_pid = reinterpret_cast<int *>(s_min + PL.id);
     if constexpr (kPol != 0) load_pol_consts(pf.P, s_pc, tid, NT);
+    // the strip sort's look-back words and ticket, zero again for the next step
+    if (blockIdx.x == 0)
+        for (int i = tid; i < a.n_status; i += NT) a.status[i] = 0u;
     __syncthreads();
     const int pos = p0 + slot;
     if constexpr (G == 1 && kPol == 0) {
@@ -1303,7 +1567,7 @@ int scan_blocks_for(int64_t C, int64_t max_env_cells) {
     return max_env_cells <= kScanTile ? 0 : (int)((C + kTile2 - 1) / kTile2);
 }
 
-void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
+void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a, int64_t S) {
     const int64_t nb = (C + kTile2 - 1) / kTile2;  // partials of the two-level scan
     a->key = cv.take<int32_t>(G);
     a->slot = cv.take<int32_t>(G);
@@ -1316,6 +1580,81 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
     a->envs[0] = cv.take<DevEnv>(E);
     a->envs[1] = cv.take<DevEnv>(E);
     a->base = cv.take<int32_t>(E + 1);
+    a->strip_env = S > 0 ? cv.take<int32_t>(S) : nullptr;
+    a->status = S > 0 ? cv.take<uint32_t>(S + 1) : nullptr;
+    a->n_status = S > 0 ? (int32_t)(S + 1) : 0;
+}
+
+bool strips_allowed(const DevEnv &d) {
+    // at most one column per step (half a column leaves room for the rounding
+    // of the column boundaries), and one column's cells fit the block
+    return d.ncy <= kStripCells && d.s_max <= 0.5f * d.cw;
+}
+
+int strip_cols_for(const DevEnv &d, int64_t G) {
+    // about G / 512 agents per strip (at least 512, at most 4,096), so a
+    // large batch gives hundreds of blocks and a small one still several
+    const double target = std::min(4096.0, std::max(512.0, (double)G / 512.0));
+    const double per_col = (double)std::max(d.n, 1) / d.ncx;
+    int cols = (int)std::lround(target / per_col);
+    cols = std::max(1, std::min(cols, kStripCells / d.ncy));
+    return std::min(cols, d.ncx);
+}
+
+// LDS of a strip block: cells, then 16 bytes per listed agent.
+static size_t strip_lds_bytes(int cells, int cap) {
+    return ((size_t)((cells + 3) & ~3) + 4 * (size_t)cap) * sizeof(int);
+}
+
+void plan_strip_launch(StepPlan *p, const DevEnv *envs, int n_envs) {
+    int cells = 1;
+    double own = 1.0;
+    for (int e = 0; e < n_envs; ++e) {
+        const DevEnv &d = envs[e];
+        cells = std::max(cells, d.strip_cols * d.ncy);
+        own = std::max(own, (double)std::max(d.n, 1) / d.ncx * d.strip_cols);
+    }
+    // half again the largest expected strip (uniform density), within 64 KiB
+    const int fit = (int)((65536 / sizeof(int) - ((cells + 3) & ~3)) / 4);
+    p->strip_cells = cells;
+    p->strip_cap = std::max(0, std::min((int)std::ceil(1.5 * own), fit));
+}
+
+// Whether every block of the plan's strip sort is resident at once (4 per CU
+// by waves, 8 per block; fewer by LDS), so the block index can serve as the
+// strip: a strip then only ever waits for strips that are running.  The CU
+// count is read once per device.
+static int strip_direct(const StepPlan &p) {
+    static int cus_of[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cus_of[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            return 0;
+        cus_of[dev] = cus;
+    }
+    const int per_cu = std::min<int>(4, (int)(160 * 1024 / strip_lds_bytes(p.strip_cells, p.strip_cap)));
+    return p.strips <= (int64_t)cus_of[dev] * per_cu ? 1 : 0;
+}
+
+int64_t assign_strips(DevEnv *const *tabs, int n_tabs, int n_envs, int64_t G,
+                      std::vector<int32_t> *strip_env) {
+    int64_t S = 0;
+    if (strip_env) strip_env->clear();
+    for (int e = 0; e < n_envs; ++e) {
+        const int cols = strip_cols_for(tabs[0][e], G);
+        const int ns = (tabs[0][e].ncx + cols - 1) / cols;
+        for (int k = 0; k < n_tabs; ++k) {
+            tabs[k][e].strip_base = (int32_t)S;
+            tabs[k][e].strip_cols = cols;
+            tabs[k][e].n_strips = ns;
+        }
+        if (strip_env) strip_env->insert(strip_env->end(), ns, e);
+        S += ns;
+    }
+    return S;
 }
 
 // Descriptor tables and agent offsets of a one-env plan, written from the
@@ -1324,6 +1663,7 @@ void carve_sort(Carver &cv, int64_t G, int64_t C, int E, SortArrays *a) {
 __global__ void k_bind_one(SortArrays a, DevEnv d0, DevEnv d1, int32_t n, int64_t C) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < C) a.count[i] = 0;
+    if (i < a.n_status) a.status[i] = 0u;
     if (i == 0) {
         a.envs[0][0] = d0;
         a.envs[1][0] = d1;
@@ -1334,7 +1674,7 @@ __global__ void k_bind_one(SortArrays a, DevEnv d0, DevEnv d1, int32_t n, int64_
 
 hipError_t launch_bind_one(const StepPlan &p, const DevEnv &d0, const DevEnv &d1, int32_t n,
                            hipStream_t s) {
-    const int64_t c = p.C > 0 ? p.C : 1;
+    const int64_t c = std::max<int64_t>(std::max<int64_t>(p.C, p.a.n_status), 1);
     hipLaunchKernelGGL(k_bind_one, dim3(blocks_for(c, 256)), dim3(256), 0, s, p.a, d0, d1, n, p.C);
     return hipGetLastError();
 }
@@ -1344,6 +1684,9 @@ bool plan_fuses_policy(const StepPlan &p) { return !p.tag && (p.lanes == 1 || p.
 hipError_t launch_clear(const StepPlan &p, hipStream_t s) {
     const int64_t n = p.C > 0 ? p.C : 1;
     hipLaunchKernelGGL(k_clear, dim3(blocks_for(n, 256)), dim3(256), 0, s, p.a.count, p.C);
+    if (p.a.n_status > 0)
+        hipLaunchKernelGGL(k_clear, dim3(blocks_for(p.a.n_status, 256)), dim3(256), 0, s,
+                           reinterpret_cast<int32_t *>(p.a.status), (int64_t)p.a.n_status);
     return hipGetLastError();
 }
 
@@ -1399,6 +1742,15 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
     const unsigned nb = blocks_for(G, kBlock);
     switch (phase) {
         case kPhaseMove:
+            if (p.env_sort_recs == 0 && p.strips > 0 && p.strip_now) {
+                hipLaunchKernelGGL(k_strip_sort<kStripNT>, dim3((unsigned)p.strips), dim3(kStripNT),
+                                   strip_lds_bytes(p.strip_cells, p.strip_cap), s, p.a, envs,
+                                   p.n_envs, C, G, (int)p.strips, do_move,
+                                   reinterpret_cast<const float2 *>(act), p.tag,
+                                   reinterpret_cast<float2 *>(act_copy), p.strip_cap,
+                                   strip_direct(p));
+                break;
+            }
             if (p.env_sort_recs > 0) {
                 const size_t lds = (size_t)p.max_env_cells * sizeof(int);
                 const float2 *a2 = reinterpret_cast<const float2 *>(act);
@@ -1418,7 +1770,7 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
                                reinterpret_cast<float2 *>(act_copy));
             break;
         case kPhaseScan:
-            if (p.env_sort_recs > 0) break;  // done inside k_env_sort
+            if (p.env_sort_recs > 0 || (p.strips > 0 && p.strip_now)) break;  // one-kernel sorts
             if (p.scan_blocks == 0) {
                 if (p.max_env_cells <= 2048)
                     hipLaunchKernelGGL((k_scan_env<256, 8>), dim3(p.n_envs), dim3(256), 0, s,
@@ -1441,7 +1793,7 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
             }
             break;
         case kPhaseScatter:
-            if (p.env_sort_recs > 0) break;  // done inside k_env_sort
+            if (p.env_sort_recs > 0 || (p.strips > 0 && p.strip_now)) break;  // one-kernel sorts
             hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, p.a, envs, p.n_envs, G,
                                p.tag);
             break;

@@ -129,13 +129,23 @@ int64_t running_agents(const srv_t *S, int64_t *cells) {
     return g;
 }
 
+// Columns of an env's grid: at most one strip each, so a bound on the strips
+// of any plan that holds the env.
+int64_t env_columns(const env_t *env) { return env_descriptor(env, 0).ncx; }
+
+int64_t running_columns(const srv_t *S) {
+    int64_t c = 0;
+    for (int64_t id : S->running) c += env_columns(S->reqs.at(id).env);
+    return c;
+}
+
 // (Re)allocate the sort scratch for G agents / C cells / E envs; restores the
 // previous block on failure.
-bool resize_scratch(srv_t *S, int64_t G, int64_t C, int E) {
+bool resize_scratch(srv_t *S, int64_t G, int64_t C, int E, int64_t cols) {
     const Block old = S->scratch;
     if (old.live) S->alloc.release(old.off, old.bytes);
     Block nb;
-    nb.bytes = sort_scratch_bytes(G, C, E > 0 ? E : 1);
+    nb.bytes = sort_scratch_bytes(G, C, E > 0 ? E : 1, cols);
     if (S->alloc.alloc(nb.bytes, &nb.off)) {
         nb.live = true;
         S->scratch = nb;
@@ -181,7 +191,8 @@ int try_admit(srv_t *S, Request &r) {
     }
     int64_t C;
     const int64_t G = running_agents(S, &C);
-    if (!resize_scratch(S, G + r.p.n_agents, C + env_cell_count(r.env), (int)S->running.size() + 1)) {
+    if (!resize_scratch(S, G + r.p.n_agents, C + env_cell_count(r.env), (int)S->running.size() + 1,
+                        running_columns(S) + env_columns(r.env))) {
         release_request_blocks(S, r);
         return ENV_EAGAIN;
     }
@@ -241,8 +252,19 @@ int rebuild_plan(srv_t *S) {
         c += env_cell_count(r.env);
     }
     S->base.push_back((int32_t)g);
+    // strips of the running envs (the strip sort), when every env allows it
+    bool strips_ok = true;
+    for (const DevEnv &d : S->tab[0]) strips_ok = strips_ok && strips_allowed(d);
+    std::vector<int32_t> strip_env;
+    int64_t n_strips = 0;
+    if (strips_ok && !S->tab[0].empty()) {
+        DevEnv *tabs[2] = {S->tab[0].data(), S->tab[1].data()};
+        n_strips = assign_strips(tabs, 2, (int)S->running.size(), g, &strip_env);
+    }
     Carver cv{S->arena + S->scratch.off, 0};
-    carve_sort(cv, g, c, (int)S->running.size(), &S->plan.a);
+    carve_sort(cv, g, c, (int)S->running.size(), &S->plan.a, n_strips);
+    S->plan.strips = (int)n_strips;
+    if (n_strips > 0) plan_strip_launch(&S->plan, S->tab[0].data(), (int)S->running.size());
     S->plan.n_envs = (int)S->running.size();
     S->plan.G = g;
     S->plan.C = c;
@@ -271,6 +293,9 @@ int rebuild_plan(srv_t *S) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->plan.a.base, S->base.data(), S->base.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, S->stream);
+    if (e == hipSuccess && n_strips > 0)
+        e = hipMemcpyAsync(S->plan.a.strip_env, strip_env.data(), strip_env.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, S->stream);
     if (e == hipSuccess) e = launch_clear(S->plan, S->stream);
     if (e != hipSuccess) return set_error(ENV_EHIP, "serving plan upload: %s", hipGetErrorString(e));
     S->table = 0;
@@ -287,7 +312,7 @@ size_t srv_request_bytes(const env_params_t *p) {
     const size_t ws = align_up(env_workspace_bytes(p), 256);
     // its share of the batch sort scratch: per agent and per cell arrays
     const int64_t n = p->n_agents;
-    const size_t share = sort_scratch_bytes(n, cell_count_for(*p), 1);
+    const size_t share = sort_scratch_bytes(n, cell_count_for(*p), 1, column_count_for(*p));
     return ws + io_bytes(*p) + share;
 }
 
@@ -372,6 +397,9 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
     if (rc != ENV_OK) return rc;
     // the policy on every running request's view (its own launch: run inside
     // the view sweep it was measured slower), then one batched step
+    bool sorted = true;  // every running env's records in cell order (after its reset)
+    for (int64_t id : S->running) sorted = sorted && env_sorted(S->reqs.at(id).env);
+    S->plan.strip_now = sorted ? 1 : 0;
     hipError_t e = policy_launch_envs(S->pol, S->plan, S->table, S->stream);
     if (e == hipSuccess)
         e = launch_step(S->plan, S->table, 1, nullptr, nullptr, nullptr, 1, S->stream);
@@ -416,7 +444,7 @@ int srv_tick(srv_t *S, int32_t *n_running, int64_t *agents) {
         int64_t C;
         const int64_t G = running_agents(S, &C);
         if (!S->running.empty()) {
-            resize_scratch(S, G, C, (int)S->running.size());
+            resize_scratch(S, G, C, (int)S->running.size(), running_columns(S));
         } else if (S->scratch.live) {  // an idle server holds no scratch: the arena is whole
             S->alloc.release(S->scratch.off, S->scratch.bytes);
             S->scratch.live = false;

@@ -625,7 +625,8 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
 // row from the strips of the env before it by decoupled look-back, and
 // writes its agents in cell order and its cells' starts.
 constexpr int kStripNT = 512;
-constexpr int kStripR = 4;  // old records per thread and round
+constexpr int kStripR = 4;   // old records per thread and round (placing by a second pass)
+constexpr int kStripR1 = 4;  // old records per thread and round of the counting pass (8: no faster, 89 VGPRs)
 constexpr uint32_t kStripAgg = 1u << 30;   // look-back word: the strip's own count is set
 constexpr uint32_t kStripIncl = 1u << 31;  // the count of the env's strips up to this one is set
 constexpr uint32_t kStripVal = kStripAgg - 1;
@@ -751,16 +752,58 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
             for (int i0 = s_rng[r] + tid; i0 < s_rng[r + 1]; i0 += R * NT)
                 round(i0, s_rng[r + 1], use);
     };
-    // pass 1: count the strip's agents per cell, listing the first `cap` of them
-    each_old([&](int i, const float4 &, int, float2 av, int cell) {
-        atomicAdd(&s_cells[cell], 1);
-        const int k = atomicAdd(&s_own, 1);
-        if (k < cap) {
-            s_oi[k] = i;
-            s_oc[k] = cell;
-            s_oa[k] = av;
+    // pass 1: count the strip's agents per cell, listing the first `cap` of
+    // them (one LDS atomic per wave and record slot for the list position);
+    // kStripR1 records per thread and round
+    const int lane = tid & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    constexpr int R1 = kStripR1;
+    for (int r = 0; r < 4; r += 2)
+        for (int i0 = s_rng[r] + tid; i0 < s_rng[r + 1]; i0 += R1 * NT) {
+            const int i1 = s_rng[r + 1];
+            int id[R1];
+            float4 m[R1];
+            float2 av[R1];
+#pragma unroll
+            for (int u = 0; u < R1; ++u) {
+                const int i = i0 + u * NT;
+                id[u] = i < i1 ? E.id_cur[i] : 0;
+                m[u] = i < i1 ? E.rec_cur[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int u = 0; u < R1; ++u) {
+                const int i = i0 + u * NT;
+                av[u] = make_float2(0.0f, 0.0f);
+                if (do_move && i < i1)
+                    av[u] = act ? act[E.agent_base + id[u]]
+                                : reinterpret_cast<const float2 *>(E.act)[id[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < R1; ++u) {
+                const int i = i0 + u * NT;
+                int cell = -1;
+                if (i < i1) {
+                    const float4 mm = do_move ? move_record(E, m[u], av[u]) : m[u];
+                    const int cx = cell_of(mm.x, E.inv_cx, ncx);
+                    if (cx >= c0 && cx < c1) cell = cx * ncy + cell_of(mm.y, E.inv_cy, ncy) - cbase;
+                }
+                const uint64_t mask = __ballot(cell >= 0);
+                if (mask == 0) continue;
+                const int leader = __builtin_ctzll(mask);
+                int wbase = 0;
+                if (lane == leader) wbase = atomicAdd(&s_own, __popcll(mask));
+                wbase = __shfl(wbase, leader, 64);
+                if (cell >= 0) {
+                    atomicAdd(&s_cells[cell], 1);
+                    const int k = wbase + __popcll(mask & below);
+                    if (k < cap) {
+                        s_oi[k] = i;
+                        s_oc[k] = cell;
+                        s_oa[k] = av[u];
+                    }
+                }
+            }
         }
-    });
     __syncthreads();
     // exclusive scan of the counts: thread t owns cells [t k, t k + k)
     const int per = (ncell + NT - 1) / NT;
@@ -1620,10 +1663,10 @@ void plan_strip_launch(StepPlan *p, const DevEnv *envs, int n_envs) {
     p->strip_cap = std::max(0, std::min((int)std::ceil(1.5 * own), fit));
 }
 
-// Whether every block of the plan's strip sort is resident at once (4 per CU
-// by waves, 8 per block; fewer by LDS), so the block index can serve as the
-// strip: a strip then only ever waits for strips that are running.  The CU
-// count is read once per device.
+// Whether every block of the plan's strip sort is resident at once (as the
+// runtime's occupancy calculation for this kernel and LDS size says), so the
+// block index can serve as the strip: a strip then only ever waits for
+// strips that are running.  The CU count is read once per device.
 static int strip_direct(const StepPlan &p) {
     static int cus_of[64];
     int dev = 0;
@@ -1635,7 +1678,11 @@ static int strip_direct(const StepPlan &p) {
             return 0;
         cus_of[dev] = cus;
     }
-    const int per_cu = std::min<int>(4, (int)(160 * 1024 / strip_lds_bytes(p.strip_cells, p.strip_cap)));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_strip_sort<kStripNT>), kStripNT,
+            strip_lds_bytes(p.strip_cells, p.strip_cap)) != hipSuccess)
+        return 0;
     return p.strips <= (int64_t)cus_of[dev] * per_cu ? 1 : 0;
 }
 

@@ -625,6 +625,7 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
 // row from the strips of the env before it by decoupled look-back, and
 // writes its agents in cell order and its cells' starts.
 constexpr int kStripNT = 512;
+constexpr int kXcds = 8;     // MI355X: accelerator dies (XCDs), each with its own L2
 constexpr int kStripR = 4;   // old records per thread and round (placing by a second pass)
 constexpr int kStripR1 = 4;  // old records per thread and round of the counting pass (8: no faster, 89 VGPRs)
 constexpr uint32_t kStripAgg = 1u << 30;   // look-back word: the strip's own count is set
@@ -672,13 +673,22 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
     __shared__ int s_rng[4];
     const int tid = threadIdx.x;
     if (tid == 0) {
-        // with few strips every block is resident at once and the block index
-        // serves; otherwise a ticket makes strips start in order
-        s_tk = direct ? (int)blockIdx.x : (int)atomicAdd(&a.status[S], 1u);
+        // With few strips every block is resident at once and the block index
+        // picks the strip: blocks go to the XCDs round robin, and XCD x takes
+        // the x-th run of `direct` consecutive strips, so an env's strips share
+        // one or two XCDs' L2 for their action gathers.  Otherwise a ticket
+        // makes strips start in order.
+        if (direct) {
+            const int x = (int)blockIdx.x % kXcds, k = (int)blockIdx.x / kXcds;
+            s_tk = k < direct ? x * direct + k : S;
+        } else {
+            s_tk = (int)atomicAdd(&a.status[S], 1u);
+        }
         s_own = 0;
     }
     __syncthreads();
     const int t = s_tk;
+    if (t >= S) return;  // a block past the last strip (direct mode padding)
     const DevEnv &E = envs[n_envs == 1 ? 0 : a.strip_env[t]];
     const int ls = t - E.strip_base, nst = E.n_strips, ncx = E.ncx, ncy = E.ncy, n = E.n;
     const int c0 = ls * E.strip_cols, c1 = ls == nst - 1 ? ncx : c0 + E.strip_cols;
@@ -1683,7 +1693,9 @@ static int strip_direct(const StepPlan &p) {
             &per_cu, reinterpret_cast<const void *>(k_strip_sort<kStripNT>), kStripNT,
             strip_lds_bytes(p.strip_cells, p.strip_cap)) != hipSuccess)
         return 0;
-    return p.strips <= (int64_t)cus_of[dev] * per_cu ? 1 : 0;
+    // the padded grid (a multiple of kXcds blocks) must be resident too
+    const int64_t blocks = (p.strips + kXcds - 1) / kXcds * kXcds;
+    return blocks <= (int64_t)cus_of[dev] * per_cu ? 1 : 0;
 }
 
 int64_t assign_strips(DevEnv *const *tabs, int n_tabs, int n_envs, int64_t G,
@@ -1790,12 +1802,14 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
     switch (phase) {
         case kPhaseMove:
             if (p.env_sort_recs == 0 && p.strips > 0 && p.strip_now) {
-                hipLaunchKernelGGL(k_strip_sort<kStripNT>, dim3((unsigned)p.strips), dim3(kStripNT),
+                // direct: strips per XCD (blocks = kXcds x that, the last few idle)
+                const int per_xcd = strip_direct(p) ? (int)((p.strips + kXcds - 1) / kXcds) : 0;
+                const unsigned nblk = per_xcd ? (unsigned)(per_xcd * kXcds) : (unsigned)p.strips;
+                hipLaunchKernelGGL(k_strip_sort<kStripNT>, dim3(nblk), dim3(kStripNT),
                                    strip_lds_bytes(p.strip_cells, p.strip_cap), s, p.a, envs,
                                    p.n_envs, C, G, (int)p.strips, do_move,
                                    reinterpret_cast<const float2 *>(act), p.tag,
-                                   reinterpret_cast<float2 *>(act_copy), p.strip_cap,
-                                   strip_direct(p));
+                                   reinterpret_cast<float2 *>(act_copy), p.strip_cap, per_xcd);
                 break;
             }
             if (p.env_sort_recs > 0) {

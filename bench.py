@@ -141,7 +141,7 @@ def bench_batched(flock, batch, K, W, seed, timed_reps=20, tag=False, reps=5):
             "latency_kind": "one-step graph replays, HIP events",
             "phase_ms": {"move_count": float(ph[0]), "scan": float(ph[1]),
                          "scatter": float(ph[2]), "sweep": float(ph[3])},
-            "fused_sort": bool(ph[1] == 0 and ph[2] == 0)}
+            "one_kernel_sort": bool(ph[1] == 0 and ph[2] == 0)}
 
 
 def bench_plain(env, n, K, W, seed, tag=False):

@@ -210,7 +210,9 @@ int env_step_static(env_t *env, const float *act, float *obs, float *reward, voi
 
 /* Several environments (possibly of different sizes, boxes and views;
  * equal `sectors` and ENV_FLAG_SPEED_OBS) stepped together by one sequence
- * of launches.  Agents of env k
+ * of launches: Sec. 2.1 has the engine update all entities of a timestep in
+ * parallel on the GPU, and Sec. 5 trains many independent environments at
+ * once; a batch is such a set sharing one launch.  Agents of env k
  * occupy rows [off[k], off[k+1]) of the batch-wide act/obs/reward arrays,
  * with off[k] = sum of n_agents of envs 0..k-1 (see env_batch_offsets).
  * Results are bitwise identical to stepping each env with env_step. */
@@ -225,7 +227,8 @@ int env_batch_create(env_t *const *envs, int n_envs, void *ws, size_t bytes,
                      env_batch_t **out);
 void env_batch_destroy(env_batch_t *b);
 
-/* As env_set_sweep_lanes, for the batched step (0 = chosen from the
+/* As env_set_sweep_lanes, for the batched step (Sec. 4: the sweep that
+ * builds every agent's view; 0 = chosen from the
  * agent-weighted mean of the envs' expected candidates).  Drops captured
  * graphs when the choice changes. */
 int env_batch_set_sweep_lanes(env_batch_t *b, int lanes);
@@ -247,15 +250,21 @@ int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes);
  * the issue-bound sweep.  ENV_EINVAL for a NULL batch. */
 int env_batch_set_policy_fusion(env_batch_t *b, int on);
 
-/* off[n_envs + 1] (host) receives the row offsets described above. */
+/* off[n_envs + 1] (host) receives the row offsets described above
+ * (the per-agent arrays of Sec. 4.1 laid end to end).  ENV_EINVAL for a
+ * NULL batch or off. */
 int env_batch_offsets(const env_batch_t *b, int64_t *off);
 
-/* One step of every env in the batch.  act: device [G][2], obs: device
- * [G][d] (d as for env_step), reward: device [G], G = off[n_envs]. */
+/* One step of every env in the batch (Sec. 4.1, as env_step; Sec. 2.1: all
+ * agents of all envs in one timestep).  act: device [G][2], obs: device
+ * [G][d] (d as for env_step), reward: device [G], G = off[n_envs]; all
+ * caller-owned, agent order.  ENV_EINVAL for NULL arguments, ENV_EHIP when
+ * a launch fails. */
 int env_step_batched(env_batch_t *b, const float *act, float *obs, float *reward,
                      void *stream);
 
-/* k_steps consecutive batched steps replayed from a captured HIP graph.
+/* k_steps consecutive batched steps (Sec. 2.1's discrete timesteps, each as
+ * env_step_batched) replayed from a captured HIP graph.
  * act: device [k_steps][G][2] (step-major), obs: device [G][d] (final view),
  * reward: device [k_steps][G].  The graph is captured on the first call and
  * re-captured when any argument changes. */
@@ -269,8 +278,9 @@ int env_batch_capture(env_batch_t *b, int k_steps, const float *act, float *obs,
 
 /* One env_step_batched whose four phases are bracketed by HIP events on
  * `stream`: phase_ms[0] move + cell count, [1] scan, [2] scatter, [3]
- * neighbour sweep (milliseconds).  Batches of many small envs sort each
- * env in one kernel (move, count, scan and scatter together): phase_ms[0]
+ * neighbour sweep (milliseconds).  Where one kernel sorts (each env of a
+ * batch of many small envs, or each strip of grid columns once the batch is
+ * in cell order) it moves, counts, scans and scatters together: phase_ms[0]
  * is then that kernel and [1], [2] are 0.  Synchronises the stream.  For
  * profiling; results are the same as env_step_batched. */
 int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *reward,
@@ -396,7 +406,11 @@ int gr_opinion_step(int64_t n, int64_t n_edges, const int64_t *row_ptr, const in
 
 /* -------------------------------------------------------------- serving */
 
-/* Continuous-batching server.  `arena` (device, `arena_bytes`) is the HBM
+/* Continuous-batching server.  The paper serves nothing: this is a systems
+ * pattern round its loop of Sec. 4.3 and Fig. 5 (the shared policy acts on
+ * every agent's view, the env steps, state stays in device memory as in
+ * Sec. 2.2), with episodes of different sizes joining and leaving a running
+ * batch.  `arena` (device, `arena_bytes`) is the HBM
  * budget: each admitted request's env workspace, view/action/reward rows and
  * the tick's batch scratch are carved from it.  At most max_slots requests
  * run at once.  All requests share `pol`: their view row length d must
@@ -407,14 +421,15 @@ int srv_create(void *arena, size_t arena_bytes, int max_slots, pol_t *pol,
                void *stream, srv_t **out);
 void srv_destroy(srv_t *srv);
 
-/* Queue an episode request: parameters, initial state (host FP32 x, y, th,
- * s, each [n]) and episode length.  Never blocks; *id receives the request
+/* Queue an episode request: parameters (Sec. 4.1), initial state (host FP32
+ * x, y, th, s, each [n], copied before return) and episode length.  Never blocks; *id receives the request
  * id.  Returns ENV_OK when admitted at once, ENV_EAGAIN when queued (no slot
  * or no memory yet), ENV_ENOMEM when the request could never fit. */
 int srv_submit(srv_t *srv, const env_params_t *p, const float *x, const float *y,
                const float *th, const float *s, int steps, int64_t *id);
 
-/* One serving tick: admit queued requests that now fit (in arrival order; a
+/* One serving tick, one step of Fig. 5's loop for every running episode:
+ * admit queued requests that now fit (in arrival order; a
  * later request that fits may pass a waiting one, but once the head of the
  * queue has waited 32 ticks nothing passes it until it is admitted), run one closed-loop
  * batched step over all running requests, retire those that finished.
@@ -422,10 +437,14 @@ int srv_submit(srv_t *srv, const env_params_t *p, const float *x, const float *y
  * Synchronises the stream at the end of the tick. */
 int srv_tick(srv_t *srv, int32_t *n_running, int64_t *agents);
 
-/* *state: 0 queued, 1 running, 2 finished; *steps_done: steps so far. */
+/* *state: 0 queued, 1 running, 2 finished; *steps_done: steps so far.
+ * ENV_ENOTFOUND for an unknown id (or one whose result was taken). */
 int srv_poll(srv_t *srv, int64_t id, int32_t *state, int32_t *steps_done);
 
-/* Per-agent FP64 returns of a finished request (host [n]); frees its record. */
+/* Per-agent FP64 returns of a finished request (host [n]; the undiscounted
+ * sum of Eq. (1)'s rewards over the episode, agent order); frees its record.
+ * ENV_ESTATE while it is queued or runs, ENV_ENOTFOUND for an unknown id,
+ * ENV_EINVAL for a wrong n. */
 int srv_result(srv_t *srv, int64_t id, double *returns_host, int64_t n);
 
 /* Arena bytes one request with these parameters occupies (0 if invalid). */

@@ -947,9 +947,10 @@ int env_step_batched_timed(env_batch_t *b, const float *act, float *obs, float *
     for (int k = 0; k < 4 && e == hipSuccess; ++k)
         e = hipEventElapsedTime(&phase_ms[k], b->events[k], b->events[k + 1]);
     if (e != hipSuccess) return hip_fail(e, "env_step_batched_timed");
-    // a fused per-env sort launches nothing for the scan and scatter phases:
-    // what their events bracket is event overhead only
-    if (b->plan.env_sort_recs > 0) phase_ms[1] = phase_ms[2] = 0.0f;
+    // the one-kernel sorts (per env, per strip) launch nothing for the scan and
+    // scatter phases: what their events bracket is event overhead only
+    if (b->plan.env_sort_recs > 0 || (b->plan.strips > 0 && b->plan.strip_now))
+        phase_ms[1] = phase_ms[2] = 0.0f;
     return ENV_OK;
 }
 

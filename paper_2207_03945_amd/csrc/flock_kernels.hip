@@ -1004,9 +1004,10 @@ __device__ __forceinline__ int sector_oct(float dx, float dy, float c, float s) 
                 (mn > 0.66817863791929891f * mx ? 1 : 0);  // tan(pi/16), tan(pi/8), tan(3 pi/16)
         }
     }
-    int k = aw > au ? 2 * M - 1 - j : j;
-    k = u < 0.0f ? 4 * M - 1 - k : k;
-    return w < 0.0f ? 8 * M - 1 - k : k;
+    // mirroring within [0, 2^b) is an XOR with 2^b - 1: the three mirrors
+    // (past 45 degrees, past 90, past 180) combine into one mask
+    const int f = (aw > au ? 2 * M - 1 : 0) ^ (u < 0.0f ? 4 * M - 1 : 0) ^ (w < 0.0f ? 8 * M - 1 : 0);
+    return j ^ f;
 }
 
 // View sector of the bearing of (dx, dy) for a limited field of view: the
@@ -1048,7 +1049,8 @@ struct ViewK {
     int v;
 };
 
-// Test candidates [q, q1) against the lane's agent: distance test, and for a
+// Test candidate qq against the lane's agent (ok: the slot holds a candidate
+// other than the agent itself): distance test, and for a
 // neighbour the count, the collision count and the per-sector minimum (an
 // LDS atomic min on the agent's own minima, S words apart).  The sector is
 // computed for every candidate (branch-free); only the LDS update is
@@ -1065,10 +1067,9 @@ struct ViewK {
 // zero shift is left out: x + 0 = x for the nonnegative coordinates here).
 template <int S, bool kFov, bool kTag, int kM, bool kShiftX, bool kShiftY>
 __device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__restrict__ stype,
-                                          int ti, const float2 pj, int qq, int self, float offx,
+                                          int ti, const float2 pj, int qq, bool ok, float offx,
                                           float xi, float offy, float yi, bool minimg, float L,
-                                          float r2, float c2, const ViewK &K, int &nb, int &col,
-                                          bool valid = true) {
+                                          float r2, float c2, const ViewK &K, int &nb, int &col) {
     float dx, dy;
     if (minimg) {
         dx = min_image_delta(pj.x, xi, L);
@@ -1078,14 +1079,14 @@ __device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__r
         dy = (kShiftY ? pj.y + offy : pj.y) - yi;
     }
     const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-    const bool nbr = valid && d2 < r2 && qq != self;
+    const bool nbr = ok && d2 < r2;
     int ch = 0;  // view channel offset (sectors)
     if constexpr (kTag) {
         const int tj = stype[qq];
         nb += (nbr && tj == 0) ? 1 : 0;
         col += (nbr && tj != ti && d2 < c2) ? 1 : 0;
         ch = tj * K.v;
-    } else {
+    } else if constexpr (kFov) {
         nb += nbr ? 1 : 0;
         col += (nbr && d2 < c2) ? 1 : 0;
     }
@@ -1096,7 +1097,15 @@ __device__ __forceinline__ void test_pair(uint32_t *smin_own, const uint8_t *__r
         int k;
         if constexpr (kM > 0) k = sector_oct<kM>(dx, dy, K.c, K.s);
         else k = sector_of(dx, dy, K.c, K.s, K.vf, K.v);
-        if (nbr) atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
+        if (nbr) {
+            // full view: the counts go with the neighbour's branch, which some
+            // lane of the wave takes on nearly every slot anyway
+            if constexpr (!kTag) {
+                ++nb;
+                if (d2 < c2) ++col;
+            }
+            atomicMin(&smin_own[(ch + k) * S], __float_as_uint(d2));
+        }
     }
 }
 
@@ -1107,9 +1116,9 @@ __device__ __forceinline__ void sweep_run(uint32_t *smin_own, const float2 *__re
                                           float offy, float yi, bool minimg, float L, float r2,
                                           float c2, const ViewK &K, int &nb, int &col) {
     auto test = [&](const float2 pj, int qq, bool valid) {
-        test_pair<S, kFov, kTag, kM, kShiftX, kShiftY>(smin_own, stype, ti, pj, qq, self, offx, xi,
-                                                       offy, yi, minimg, L, r2, c2, K, nb, col,
-                                                       valid);
+        test_pair<S, kFov, kTag, kM, kShiftX, kShiftY>(smin_own, stype, ti, pj, qq,
+                                                       valid && qq != self, offx, xi, offy, yi,
+                                                       minimg, L, r2, c2, K, nb, col);
     };
     // UNROLL candidates per lane and step, those past the run's end masked
     // (the position arrays are padded for the reads)
@@ -1170,7 +1179,9 @@ constexpr int kUnrollMax = 4;
 // queued in registers: lanes switch runs at different steps, so whatever a
 // switch costs is paid by the whole wave on nearly every step.
 constexpr bool kFlatRuns = true;
-constexpr int kFlatUnroll = 6;  // candidates per step (4: 60.5 us, 6: 59.8, 8: 62.0 at 1M agents)
+// Candidates per step of the flat walk; step of 200 x 5,000 agents, 16 sectors:
+// 4 -> 70.1 us, 5 -> 71.0, 6 -> 70.6, 8 -> 73.2.
+constexpr int kFlatUnroll = 4;
 // Entries past the end of the cell-order position and type arrays, so that a
 // step's reads past the last run stay inside the allocation: a lane reads at
 // most (unroll - 1) * G + G - 1 < kUnrollMax * 64 (lane groups of G <= 64)
@@ -1179,6 +1190,57 @@ constexpr int kSortPad = 256;
 static_assert(unroll_for<4>() <= kUnrollMax && unroll_for<64>() <= kUnrollMax, "unroll bound");
 static_assert(kFlatUnroll <= kSortPad + 1 && kUnrollMax * 64 <= kSortPad + 1,
               "pad the cell-order arrays for the unrolled reads");
+
+// The runs of one agent's flat walk (one lane per agent, one column either
+// side), for an agent at (fx into its column cx, y): slot c (c < 3) holds
+// column cx + c - 1's first segment, slot 3 + c its second (empty unless the
+// rows wrap), each as [rq, rq1) in cell order, with 4 bits of shift flags per
+// slot in fl (1 candidate x - L, 2 centre x - L, 4 candidate y - L, 8 centre
+// y - L).  nr: the slots up to the last nonempty one, which the walk takes in
+// order.
+struct FlatRuns {
+    int rq[6], rq1[6];
+    uint32_t fl;
+    int nr;
+};
+
+__device__ __forceinline__ void flat_runs(const RowGeom &RG, const int32_t *__restrict__ start,
+                                          int cb, int ncx, int cx, float fx, float y,
+                                          FlatRuns &F) {
+    const int ncy = RG.ncy;
+    F.fl = 0u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int lo = 0, hi = -1;
+        const bool any = column_rows(RG, fx, c - 1, y, lo, hi);
+        int ccx = cx + c - 1;
+        uint32_t fxs = 0;
+        if (ccx < 0) {
+            ccx += ncx;
+            fxs = 1;
+        } else if (ccx >= ncx) {
+            ccx -= ncx;
+            fxs = 2;
+        }
+        const int colb = cb + ccx * ncy;
+        const bool wlo = lo < 0, whi = hi >= ncy;
+        // first segment [ia, ib), second [colb, id)
+        int ia = colb + (wlo ? lo + ncy : lo);
+        int ib = colb + ((wlo || whi) ? ncy : hi + 1);
+        int id = colb + (wlo ? hi + 1 : (whi ? hi - ncy + 1 : 0));
+        if (!any) ia = ib = id = colb;
+        F.rq[c] = start[ia];
+        F.rq1[c] = start[ib];
+        F.rq[3 + c] = start[colb];
+        F.rq1[3 + c] = start[id];
+        F.fl |= (fxs | (wlo ? 4u : 0u)) << (4 * c);
+        F.fl |= (fxs | (whi ? 8u : 0u)) << (4 * (3 + c));
+    }
+    int nr = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nr = F.rq1[k] > F.rq[k] ? k + 1 : nr;
+    F.nr = nr;
+}
 
 // NT threads per block, G lanes per agent (in the new cell order): A = NT/G
 // agents per block, their sector minima v * A * 4 bytes of dynamic LDS.  G = 1
@@ -1306,78 +1368,55 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                 }
             };
             if (G == 1 && kFlatRuns && reach == 1) {
-                // The agent's runs, built once: slot c (c < 3) is column c - 1's
-                // first segment, slot 3 + c its second (empty unless the rows
-                // wrap).  Per slot 4 bits of shift flags: 1 candidate x - L,
-                // 2 centre x - L, 4 candidate y - L, 8 centre y - L.
-                int rq[6], rq1[6];
-                uint32_t fl = 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    int lo = 0, hi = -1;
-                    const bool any = column_rows(RG, fx, c - 1, me.y, lo, hi);
-                    int ccx = cx + c - 1;
-                    uint32_t fxs = 0;
-                    if (ccx < 0) {
-                        ccx += ncx;
-                        fxs = 1;
-                    } else if (ccx >= ncx) {
-                        ccx -= ncx;
-                        fxs = 2;
-                    }
-                    const int colb = cb + ccx * ncy;
-                    const bool wlo = lo < 0, whi = hi >= ncy;
-                    // first segment [ia, ib), second [colb, colb + id - colb)
-                    int ia = colb + (wlo ? lo + ncy : lo);
-                    int ib = colb + ((wlo || whi) ? ncy : hi + 1);
-                    int id = colb + (wlo ? hi + 1 : (whi ? hi - ncy + 1 : 0));
-                    if (!any) ia = ib = id = colb;
-                    rq[c] = a.start[ia];
-                    rq1[c] = a.start[ib];
-                    rq[3 + c] = a.start[colb];
-                    rq1[3 + c] = a.start[id];
-                    fl |= (fxs | (wlo ? 4u : 0u)) << (4 * c);
-                    fl |= (fxs | (whi ? 8u : 0u)) << (4 * (3 + c));
-                }
-                int q = 0, q1 = 0, left = 6;
-                float offx = 0.0f, xi = me.x, offy = 0.0f, yi = me.y;
-                // move to the next nonempty slot; false when none is left
-                auto advance = [&]() -> bool {
-                    while (left > 0) {
-                        q = rq[0];
-                        q1 = rq1[0];
-                        const uint32_t f = fl;
-#pragma unroll
-                        for (int k = 0; k < 5; ++k) {
-                            rq[k] = rq[k + 1];
-                            rq1[k] = rq1[k + 1];
-                        }
-                        fl >>= 4;
-                        --left;
-                        if (q < q1) {
-                            offx = (f & 1u) ? -L : 0.0f;
-                            xi = (f & 2u) ? me.x - L : me.x;
-                            offy = (f & 4u) ? -L : 0.0f;
-                            yi = (f & 8u) ? me.y - L : me.y;
-                            return true;
-                        }
-                    }
-                    return false;
+                FlatRuns F;
+                flat_runs(RG, a.start, cb, ncx, cx, fx, me.y, F);
+                // the current run [q, q1) and its shifts; the rest queue in F
+                int q = F.rq[0], q1 = F.rq1[0], left = F.nr;
+                uint32_t fl = F.fl;
+                float offx, xi, offy, yi;
+                auto shifts = [&]() {
+                    offx = (fl & 1u) ? -L : 0.0f;
+                    xi = (fl & 2u) ? me.x - L : me.x;
+                    offy = (fl & 4u) ? -L : 0.0f;
+                    yi = (fl & 8u) ? me.y - L : me.y;
                 };
-                bool more = advance();
-                while (more) {
+                shifts();
+                while (true) {
                     // kFlatUnroll candidates per step, those past the run's end
                     // masked (the position arrays are padded for the reads)
                     float2 pj[kFlatUnroll];
 #pragma unroll
                     for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
+                    const int rem = q1 - q, so = pos - q;  // slots in the run; the agent's own
+                    // most runs have no candidate-side shift: a step in which no
+                    // lane of the wave has one leaves out the two additions
+                    if (__any((fl & 5u) != 0u)) {
 #pragma unroll
-                    for (int u = 0; u < kFlatUnroll; ++u)
-                        test_pair<A, kFov, kTag, kM, true, true>(smin, a.stype, ti, pj[u], q + u,
-                                                                 pos, offx, xi, offy, yi, false, L,
-                                                                 r2, c2, K, nb, col, q + u < q1);
+                        for (int u = 0; u < kFlatUnroll; ++u)
+                            test_pair<A, kFov, kTag, kM, true, true>(
+                                smin, a.stype, ti, pj[u], q + u, u < rem && u != so, offx, xi,
+                                offy, yi, false, L, r2, c2, K, nb, col);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < kFlatUnroll; ++u)
+                            test_pair<A, kFov, kTag, kM, false, false>(
+                                smin, a.stype, ti, pj[u], q + u, u < rem && u != so, offx, xi,
+                                offy, yi, false, L, r2, c2, K, nb, col);
+                    }
                     q += kFlatUnroll;
-                    if (q >= q1) more = advance();
+                    if (q >= q1) {
+                        // next slot (an empty one costs a step of masked tests)
+                        if (--left <= 0) break;
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            F.rq[k] = F.rq[k + 1];
+                            F.rq1[k] = F.rq1[k + 1];
+                        }
+                        fl >>= 4;
+                        q = F.rq[0];
+                        q1 = F.rq1[0];
+                        shifts();
+                    }
                 }
             } else {
                 for (int ox = -reach; ox <= reach; ++ox) {

@@ -1381,12 +1381,19 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                     yi = (fl & 8u) ? me.y - L : me.y;
                 };
                 shifts();
-                while (true) {
-                    // kFlatUnroll candidates per step, those past the run's end
-                    // masked (the position arrays are padded for the reads)
-                    float2 pj[kFlatUnroll];
+                // kFlatUnroll candidates per step, those past the run's end
+                // masked (the position arrays are padded for the reads); each
+                // step loads the next one's before its tests: the rest of this
+                // run, else the next queued run's start (a stale but in-range
+                // start once none is left)
+                float2 pj[kFlatUnroll];
 #pragma unroll
-                    for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
+                for (int u = 0; u < kFlatUnroll; ++u) pj[u] = a.sxy[q + u];
+                while (true) {
+                    const int qn = q + kFlatUnroll < q1 ? q + kFlatUnroll : F.rq[1];
+                    float2 pn[kFlatUnroll];
+#pragma unroll
+                    for (int u = 0; u < kFlatUnroll; ++u) pn[u] = a.sxy[qn + u];
                     const int rem = q1 - q, so = pos - q;  // slots in the run; the agent's own
                     // most runs have no candidate-side shift: a step in which no
                     // lane of the wave has one leaves out the two additions
@@ -1417,6 +1424,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
                         q1 = F.rq1[0];
                         shifts();
                     }
+#pragma unroll
+                    for (int u = 0; u < kFlatUnroll; ++u) pj[u] = pn[u];
                 }
             } else {
                 for (int ox = -reach; ox <= reach; ++ox) {

@@ -1290,6 +1290,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     extern __shared__ uint32_t s_min[];  // [channels * v][A] (then the policy's, kPol)
     const int vs = kTag ? 2 * v : v;     // minima per agent
     __shared__ int s_env;
+    __shared__ float *s_orow[G == 1 && kPol == 0 ? NT : 1];  // view rows (one lane per agent)
     const int tid = threadIdx.x, slot = tid / G, li = tid % G;
     const int p0 = blockIdx.x * A;
     block_env(&s_env, a.base, n_envs, p0);
@@ -1457,6 +1458,11 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         if constexpr (kPol != 0) smin[k * A] = __float_as_uint(o);
         return o;
     };
+    // One lane per agent: rows of 4, 8, 16, 32 or 64 views (no speed column)
+    // leave the wave whole, vs / 4 lanes to a row, so that each store instruction writes
+    // 64 / (vs / 4) whole rows rather than 16 bytes of each of 64 rows.
+    const bool rows_whole =
+        G == 1 && kPol == 0 && obs_dim == vs && vs >= 4 && vs <= 64 && (vs & (vs - 1)) == 0;
     if (active) {
         const int id = load_as<kGl>(E.id_nxt, j);
         my_id = id;
@@ -1465,6 +1471,10 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         if (li == 0 && obs_dim > vs) store_as<kGl>(orow, vs, me.w);  // speed after the move (Sec. 4.1)
         if constexpr (G > 1) {
             for (int k = li; k < vs; k += G) store_as<kGl>(orow, k, view(k, inv_r));
+        } else if (rows_whole) {
+            // the views in place of the minima, the row's address beside them
+            for (int k = 0; k < vs; ++k) smin[k * A] = __float_as_uint(view(k, inv_r));
+            if constexpr (kPol == 0) s_orow[slot] = orow;
         } else if ((obs_dim & 3) == 0 && (vs & 3) == 0) {
             for (int k = 0; k < vs; k += 4) {
                 float o[4];
@@ -1493,6 +1503,25 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
         }
     } else if constexpr (kPol != 0 && G > 1) {
         if (li == 0) s_pe[slot] = -1;
+    }
+    if constexpr (G == 1 && kPol == 0) {
+        if (rows_whole) {
+            // The lanes left here are the wave's active ones, a prefix of it
+            // (in the last wave of a launch the others have returned): they
+            // share out the n_act rows' vs / 4 pieces, piece t = row t / lpr,
+            // columns 4 (t % lpr) on.
+            wave_lds_fence();
+            const int lane = tid & 63, w0 = tid - lane;
+            const int n_act = __popcll(__ballot(1));
+            const int lpr = vs >> 2, lg = __builtin_ctz(lpr);
+            for (int t = lane; t < n_act * lpr; t += n_act) {
+                const int r = t >> lg, c4 = 4 * (t & (lpr - 1));
+                const uint32_t *col4 = s_min + c4 * A + w0 + r;
+                *reinterpret_cast<float4 *>(s_orow[w0 + r] + c4) =
+                    make_float4(__uint_as_float(col4[0]), __uint_as_float(col4[A]),
+                                __uint_as_float(col4[2 * A]), __uint_as_float(col4[3 * A]));
+            }
+        }
     }
     // The policy's action of a tile's agent from its output pre-activations
     // (lanes g == 0 of a valid column write).

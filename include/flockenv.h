@@ -250,6 +250,15 @@ int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes);
  * the issue-bound sweep.  ENV_EINVAL for a NULL batch. */
 int env_batch_set_policy_fusion(env_batch_t *b, int on);
 
+/* Bound on the wait of the batch's strip sort (polling rounds; default
+ * 16384).  The sort cuts each env's grid columns into strips, one block each,
+ * and a strip takes its first output row from the running totals of the
+ * strips before it; a strip whose wait runs out counts the agents before it
+ * itself.  Results are the same for every value: 0 makes every strip count
+ * (the fallback, for tests).  Drops captured graphs when the value changes.
+ * ENV_EINVAL for a NULL batch or polls < 0. */
+int env_batch_set_strip_wait(env_batch_t *b, int polls);
+
 /* off[n_envs + 1] (host) receives the row offsets described above
  * (the per-agent arrays of Sec. 4.1 laid end to end).  ENV_EINVAL for a
  * NULL batch or off. */

@@ -829,6 +829,16 @@ int env_batch_set_policy_fusion(env_batch_t *b, int on) {
     return ENV_OK;
 }
 
+int env_batch_set_strip_wait(env_batch_t *b, int polls) {
+    if (!b) return fail(ENV_EINVAL, "batch is NULL");
+    if (polls < 0) return fail(ENV_EINVAL, "polls must be >= 0");
+    if (polls != b->plan.strip_wait) {
+        drop_graphs(b);
+        b->plan.strip_wait = polls;
+    }
+    return ENV_OK;
+}
+
 int env_batch_get_sweep_lanes(const env_batch_t *b, int32_t *lanes) {
     if (!b || !lanes) return fail(ENV_EINVAL, "NULL argument");
     *lanes = b->plan.lanes;

@@ -103,6 +103,9 @@ struct PolFuse {
 };
 
 // Launch plan of one step over a fixed set of envs.
+// Default bound on a strip's look-back wait, in polling rounds.
+constexpr int kStripWait = 1 << 14;
+
 struct StepPlan {
     SortArrays a;
     int n_envs;
@@ -120,6 +123,9 @@ struct StepPlan {
     int strip_now;          // this launch may use the strip sort (every env's records sorted)
     int strip_cells;        // cells of the plan's largest strip
     int strip_cap;          // agents a strip block lists in LDS (more: a second pass)
+    // polling rounds a strip waits for the running totals of the strips before
+    // it; when they run out it counts the agents before it itself (0: always)
+    int strip_wait = kStripWait;
 };
 
 // Workspace carving --------------------------------------------------------

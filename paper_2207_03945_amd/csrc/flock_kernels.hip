@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_move_count(SortArrays a, const DevEn
         for (int r = 0; r < R; ++r) {
             if (!live[r]) continue;
             const DevEnv &E = envs[env[r]];
+            if ((unsigned)id[r] >= (unsigned)E.n) continue;  // ids are agent indices (a guard)
             av[r] = act ? act[E.agent_base + id[r]] : reinterpret_cast<const float2 *>(E.act)[id[r]];
             if (act_copy) act_copy[E.agent_base + id[r]] = av[r];
         }
@@ -554,9 +555,11 @@ __global__ __launch_bounds__(kEnvNT) void k_env_sort(SortArrays a, const DevEnv 
             float4 m = E.rec_cur[i];
             const int id = E.id_cur[i];
             if (do_move) {
-                const float2 av =
-                    act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
-                if (act_copy) act_copy[base + id] = av;
+                float2 av = make_float2(0.0f, 0.0f);
+                if ((unsigned)id < (unsigned)n) {  // ids are agent indices (a guard)
+                    av = act ? act[base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+                    if (act_copy) act_copy[base + id] = av;
+                }
                 m = move_record(E, m, av);
             }
             if constexpr (kRegs) {
@@ -631,10 +634,35 @@ constexpr int kStripR1 = 4;  // old records per thread and round of the counting
 constexpr uint32_t kStripAgg = 1u << 30;   // look-back word: the strip's own count is set
 constexpr uint32_t kStripIncl = 1u << 31;  // the count of the env's strips up to this one is set
 constexpr uint32_t kStripVal = kStripAgg - 1;
-// Bound on one look-back wait.  Blocks take their strips in ticket order, so
-// a strip waits only for strips already running, which never wait for it:
-// the bound is never reached (it keeps a broken invariant from hanging).
-constexpr int kStripSpin = 1 << 20;
+// Look-back waits are bounded (the plan's strip_wait polling rounds).  With
+// tickets a strip waits only for strips already running.  Without them (the
+// block index picks the strip) every block is meant to be resident at once,
+// which the runtime's occupancy figure suggests but nothing guarantees: a
+// strip whose wait runs out counts the agents before it itself
+// (strip_base_by_count), so the sort stays exact and the wait bounded.
+
+// The env's agents that the step moves into columns below c0: every old
+// record of env E moved as in the strip sort (one wave, all of its lanes
+// calling).  The look-back's fallback, O(n) per call.
+__device__ int strip_base_by_count(const DevEnv &E, int c0, int do_move,
+                                   const float2 *__restrict__ act) {
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    for (int i = lane; i < E.n; i += 64) {
+        float4 m = E.rec_cur[i];
+        if (do_move) {
+            const int id = E.id_cur[i];
+            float2 av = make_float2(0.0f, 0.0f);
+            if ((unsigned)id < (unsigned)E.n)
+                av = act ? act[E.agent_base + id] : reinterpret_cast<const float2 *>(E.act)[id];
+            m = move_record(E, m, av);
+        }
+        cnt += cell_of(m.x, E.inv_cx, E.ncx) < c0 ? 1 : 0;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    return cnt;
+}
 
 // First record of env E (cell order) whose column is >= col; n when col >=
 // ncx.  Every lane of the calling wave takes part: each round probes 64
@@ -664,7 +692,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
                                                    int n_envs, int C, int G, int S, int do_move,
                                                    const float2 *__restrict__ act, int tag,
                                                    float2 *__restrict__ act_copy, int cap,
-                                                   int direct) {
+                                                   int direct, int wait) {
     // dynamic LDS: the strip's cells (counts, then each cell's next free row),
     // then up to `cap` of its agents: old record, cell, action
     extern __shared__ int s_dyn[];
@@ -743,7 +771,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
         for (int u = 0; u < R; ++u) {
             const int i = i0 + u * NT;
             av[u] = make_float2(0.0f, 0.0f);
-            if (do_move && i < i1)
+            if (do_move && i < i1 && (unsigned)id[u] < (unsigned)E.n)
                 av[u] = act ? act[E.agent_base + id[u]]
                             : reinterpret_cast<const float2 *>(E.act)[id[u]];
         }
@@ -784,7 +812,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
             for (int u = 0; u < R1; ++u) {
                 const int i = i0 + u * NT;
                 av[u] = make_float2(0.0f, 0.0f);
-                if (do_move && i < i1)
+                if (do_move && i < i1 && (unsigned)id[u] < (unsigned)E.n)
                     av[u] = act ? act[E.agent_base + id[u]]
                                 : reinterpret_cast<const float2 *>(E.act)[id[u]];
             }
@@ -844,7 +872,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
                 __hip_atomic_store(&st[t], kStripAgg | (uint32_t)total, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             int top = t - 1, spins = 0;
-            while (spins < kStripSpin) {
+            while (spins < wait) {
                 const int j = top - lane;
                 const bool valid = j >= E.strip_base;
                 const uint32_t w = valid ? __hip_atomic_load(&st[j], __ATOMIC_RELAXED,
@@ -865,6 +893,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
                 if (incl) break;
                 top -= 64;
             }
+            if (spins >= wait) base = strip_base_by_count(E, c0, do_move, act);
             if (lane == 0)
                 __hip_atomic_store(&st[t], kStripIncl | (uint32_t)(base + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -887,7 +916,7 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
         E.ret_nxt[j] = E.ret_cur[i];
         a.sxy[E.agent_base + j] = make_float2(m.x, m.y);
         if (tag) a.stype[E.agent_base + j] = id < E.n_chasers ? 1 : 0;
-        if (do_move && act_copy) act_copy[E.agent_base + id] = av;
+        if (do_move && act_copy && (unsigned)id < (unsigned)E.n) act_copy[E.agent_base + id] = av;
     };
     const int own = s_own;
     if (own <= cap) {
@@ -915,7 +944,8 @@ __global__ __launch_bounds__(NT) void k_strip_sort(SortArrays a, const DevEnv *_
                 E.ret_nxt[j] = ret[u];
                 a.sxy[E.agent_base + j] = make_float2(mm.x, mm.y);
                 if (tag) a.stype[E.agent_base + j] = id[u] < E.n_chasers ? 1 : 0;
-                if (do_move && act_copy) act_copy[E.agent_base + id[u]] = av;
+                if (do_move && act_copy && (unsigned)id[u] < (unsigned)E.n)
+                    act_copy[E.agent_base + id[u]] = av;
             }
         }
     } else {
@@ -1464,7 +1494,10 @@ __global__ __launch_bounds__(NT) void k_sweep(SortArrays a, const DevEnv *__rest
     const bool rows_whole =
         G == 1 && kPol == 0 && obs_dim == vs && vs >= 4 && vs <= 64 && (vs & (vs - 1)) == 0;
     if (active) {
-        const int id = load_as<kGl>(E.id_nxt, j);
+        // agent-order rows are addressed by id: an id out of range (a sort
+        // that went wrong) writes agent 0's rows instead of outside them
+        const int id0 = load_as<kGl>(E.id_nxt, j);
+        const int id = (unsigned)id0 < (unsigned)E.n ? id0 : 0;
         my_id = id;
         const float inv_r = E.inv_radius;
         float *orow = obs ? obs + ((size_t)E.agent_base + id) * obs_dim : E.obs + (size_t)id * obs_dim;
@@ -1886,7 +1919,8 @@ hipError_t launch_phase(const StepPlan &p, int table, StepPhase phase, int do_mo
                                    strip_lds_bytes(p.strip_cells, p.strip_cap), s, p.a, envs,
                                    p.n_envs, C, G, (int)p.strips, do_move,
                                    reinterpret_cast<const float2 *>(act), p.tag,
-                                   reinterpret_cast<float2 *>(act_copy), p.strip_cap, per_xcd);
+                                   reinterpret_cast<float2 *>(act_copy), p.strip_cap, per_xcd,
+                                   p.strip_wait);
                 break;
             }
             if (p.env_sort_recs > 0) {

@@ -112,6 +112,7 @@ def lib():
         "env_batch_set_sweep_lanes": (ctypes.c_int, [_P, ctypes.c_int]),
         "env_batch_get_sweep_lanes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "env_batch_set_policy_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
+        "env_batch_set_strip_wait": (ctypes.c_int, [_P, ctypes.c_int]),
         "env_step_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "env_batch_run": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
         "env_batch_capture": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
@@ -327,6 +328,11 @@ class Batch:
     def set_policy_fusion(self, on: bool):
         """Run the policy inside the view sweep in step_policy / rollout (off by default)."""
         check(lib().env_batch_set_policy_fusion(self.handle, 1 if on else 0))
+
+    def set_strip_wait(self, polls: int):
+        """Bound on the strip sort's look-back wait (polling rounds; 0: every
+        strip counts the agents before it itself).  Results do not depend on it."""
+        check(lib().env_batch_set_strip_wait(self.handle, int(polls)))
 
     @property
     def sweep_lanes(self) -> int:

@@ -538,6 +538,37 @@ def test_timed_step_equals_step(n_envs):
         assert ms[1] == 0.0 and ms[2] == 0.0
 
 
+@pytest.mark.parametrize("init", ["uniform", "blobs"])
+def test_strip_sort_wait_fallback_bitwise(init):
+    """The strip sort's fallback, forced from the host: with no look-back wait
+    at all every strip but an env's first counts the agents before it itself.
+    Over six steps the views, rewards, states and returns equal those of a
+    twin batch that waits, bitwise, on envs of several strips each (uniform,
+    and clustered so that strips overflow their LDS list)."""
+    sizes = [(20000, 600.0), (6000, 300.0), (900, 120.0)]
+    mk = workloads.blob_state if init == "blobs" else workloads.uniform_state
+    states = [mk(n, b, seed=40 + k) for k, (n, b) in enumerate(sizes)]
+    pair = []
+    for _ in range(2):
+        envs = [make_env(st, b, 16)[0] for st, (_, b) in zip(states, sizes)]
+        pair.append((envs, flock.Batch(envs)))
+    pair[1][1].set_strip_wait(0)
+    G = pair[0][1].n
+    obs = [torch.empty(G, 16, device="cuda") for _ in range(2)]
+    rew = [torch.empty(G, device="cuda") for _ in range(2)]
+    for t in range(6):
+        act = dev(np.concatenate([workloads.random_actions(n, seed=41, step=t, env=k)
+                                  for k, (n, _) in enumerate(sizes)]))
+        for (_, b), o, r in zip(pair, obs, rew):
+            b.step(act, o, r)
+        torch.cuda.synchronize()
+        assert torch.equal(obs[0], obs[1]) and torch.equal(rew[0], rew[1]), t
+    for ea, eb in zip(pair[0][0], pair[1][0]):
+        for x, y in zip(ea.get_state(), eb.get_state()):
+            assert torch.equal(x, y)
+        assert torch.equal(ea.returns(), eb.returns())
+
+
 # --------------------------------------------------------------------------- move arithmetic
 
 @LANES

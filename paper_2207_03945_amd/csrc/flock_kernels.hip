@@ -1034,10 +1034,20 @@ __device__ __forceinline__ int sector_oct(float dx, float dy, float c, float s) 
                 (mn > 0.66817863791929891f * mx ? 1 : 0);  // tan(pi/16), tan(pi/8), tan(3 pi/16)
         }
     }
-    // mirroring within [0, 2^b) is an XOR with 2^b - 1: the three mirrors
-    // (past 45 degrees, past 90, past 180) combine into one mask
-    const int f = (aw > au ? 2 * M - 1 : 0) ^ (u < 0.0f ? 4 * M - 1 : 0) ^ (w < 0.0f ? 8 * M - 1 : 0);
-    return j ^ f;
+    // mirroring within [0, 2^b) is an XOR with 2^b - 1, so the three mirrors
+    // (past 45 degrees, past 90, past 180) flip whole bit groups: the top bit
+    // is w < 0, the next (u < 0) ^ (w < 0), the lower ones that ^ (|w| > |u|),
+    // and j's bits flip with those (kept as lane masks, combined once)
+    const bool b3 = w < 0.0f;
+    const bool b2 = b3 ^ (u < 0.0f);
+    const bool b1 = b2 ^ (aw > au);
+    if constexpr (M == 1) {
+        return (b3 ? 4 : 0) | (b2 ? 2 : 0) | (b1 ? 1 : 0);
+    } else if constexpr (M == 2) {
+        return (b3 ? 8 : 0) | (b2 ? 4 : 0) | (b1 ? 2 : 0) | ((b1 ^ (j != 0)) ? 1 : 0);
+    } else {
+        return (b3 ? 16 : 0) | (b2 ? 8 : 0) | (b1 ? 4 : 0) | (j ^ (b1 ? 3 : 0));
+    }
 }
 
 // View sector of the bearing of (dx, dy) for a limited field of view: the

@@ -535,9 +535,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="run the main batched leg only")
-    ap.add_argument("--legs", default="plain,policy,50k,uneven,paper,tag,rollout,graph,serving",
+    ap.add_argument("--legs", default="plain,policy,50k,uneven,rollout,graph,serving",
                     help="comma list of extra legs: plain, policy, 50k, uneven, paper, tag, "
-                         "rollout, graph, serving")
+                         "rollout, graph, serving (paper and tag, the paper-scale flock and "
+                         "tag batches, only when asked for)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-baseline-child", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calib-mib", type=int, default=0,

@@ -237,7 +237,7 @@ def test_small_boxes_all_pairs_and_three_cells(box, lanes):
 
 
 @LANES
-@pytest.mark.parametrize("v", [1, 3, 8, 16, 33, 64, 128, 256])
+@pytest.mark.parametrize("v", [1, 3, 8, 16, 32, 33, 64, 128, 256])
 def test_sector_counts(v, lanes):
     st = workloads.uniform_state(2000, 120.0, seed=v)
     _one_step_case(st, 120.0, v, steps=2, lanes=lanes)

@@ -126,6 +126,21 @@ def test_tag_speed_column_and_full_view(speed, full):
     run(p, st, 4, {0, 3}, seed=2, label=f"speed={speed} full={full}")
 
 
+@pytest.mark.parametrize("sectors,full", [(8, False), (16, True), (32, False)])
+def test_tag_few_sectors_one_lane(sectors, full):
+    """One lane per agent with two channels of 8, 16 or 32 sectors (rows of 16,
+    32 or 64 values, written whole by the wave), on 700 agents: every agent
+    against the oracle over five steps; the last wave of the launch is only
+    partly filled."""
+    cfg = workloads.WORKLOADS["paper_tag1k"]
+    kw = {"sectors": sectors}
+    if full:
+        kw["fov"] = 0.0
+    p = params(cfg, n=700, chasers=64, **kw)
+    st = workloads.make_state({**cfg, "n": 700}, seed=5)
+    run(p, st, 5, set(range(5)), lanes=1, seed=5, label=f"tag sectors {sectors}")
+
+
 def test_tag_batch_equals_plain_and_two_policies():
     cfg = workloads.WORKLOADS["paper_tag1k"]
     sizes, chasers = [1100, 300, 12], [100, 27, 1]

@@ -60,7 +60,7 @@ def test_small_social_graph_every_node(lanes):
     run_case(rp, col, w, op, 0.3, 0.5, lanes, steps=3)
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 4, 16])   # 16: the setting bench.py times
 def test_million_node_graph_sampled(lanes):
     """1,000,000 nodes, ~13.8M directed edges, power-law degrees up to ~2,000."""
     rp, col, w = workloads.social_graph(1_000_000, seed=0)
